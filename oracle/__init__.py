@@ -1,0 +1,228 @@
+"""CPU oracle for the adaptive Krylov phi-function solver (Niesen & Wright).
+
+TEST INFRASTRUCTURE ONLY.  A plain double-precision C implementation of
+Algorithms 3 and 4 of the paper (with eqs. tau_0, taunew, 2-8, errest,
+phipapprox2, step, wrecurrence), loaded through ctypes.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import
+this package; the GPU library never does.  It shares no code with the GPU path.
+
+Parity status per function is listed in ``oracle.h``.  The controller's
+step-by-step trajectory has no printed worked example: parity unpinned.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "phipm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+             "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("symm", C.c_int32), ("m_init", C.c_int32),
+                ("m_max", C.c_int32), ("reorth", C.c_int32), ("adapt_m", C.c_int32),
+                ("corrector", C.c_int32), ("pad_", C.c_int32), ("tau_fixed", C.c_double),
+                ("max_attempts", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("rejected", C.c_int64), ("matvecs", C.c_int64),
+                ("expms", C.c_int64), ("t_reached", C.c_double), ("tau_last", C.c_double),
+                ("m_last", C.c_int32), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TraceRec(C.Structure):
+    _fields_ = [("t", C.c_double), ("tau", C.c_double), ("eps", C.c_double),
+                ("omega", C.c_double), ("beta", C.c_double), ("hnext", C.c_double),
+                ("anorm", C.c_double), ("tau_next", C.c_double), ("m", C.c_int32),
+                ("accepted", C.c_int32), ("step", C.c_int32), ("m_next", C.c_int32)]
+
+
+class Alg4State(C.Structure):
+    _fields_ = [("prev_rejected", C.c_int32), ("prev_branch", C.c_int32),
+                ("q_valid", C.c_int32), ("k_valid", C.c_int32), ("q_hat", C.c_double),
+                ("k_hat", C.c_double), ("eps_old", C.c_double), ("tau_old", C.c_double),
+                ("m_old", C.c_int32), ("pad_", C.c_int32)]
+
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        L.oracle_default_opts.argtypes = [C.POINTER(Opts)]
+        L.oracle_phi.argtypes = [C.c_int, C.c_double]
+        L.oracle_phi.restype = C.c_double
+        L.oracle_expm.argtypes = [C.c_int, _dp, _dp]
+        L.oracle_expm.restype = C.c_int
+        L.oracle_spmv.argtypes = [C.c_int, _ip, _ip, _dp, _dp, _dp]
+        L.oracle_is_symmetric.argtypes = [C.c_int, _ip, _ip, _dp]
+        L.oracle_is_symmetric.restype = C.c_int
+        L.oracle_krylov.argtypes = [C.c_int, _ip, _ip, _dp, _dp, C.c_int, C.c_int, C.c_int,
+                                    _dp, _dp, C.POINTER(C.c_double)]
+        L.oracle_krylov.restype = C.c_int
+        L.oracle_tau0.argtypes = [C.c_double] * 4
+        L.oracle_tau0.restype = C.c_double
+        L.oracle_cost_M.argtypes = [C.c_double]
+        L.oracle_cost_M.restype = C.c_double
+        L.oracle_cost_C1.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, C.c_double,
+                                     C.c_double]
+        L.oracle_cost_C1.restype = C.c_double
+        L.oracle_cost_C.argtypes = [C.c_double] * 3
+        L.oracle_cost_C.restype = C.c_double
+        L.oracle_alg4.argtypes = [C.POINTER(Alg4State), C.c_double, C.c_int, C.c_double,
+                                  C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_phipm.argtypes = [C.c_double, C.c_int, _ip, _ip, _dp, C.c_int, _dp,
+                                   C.POINTER(Opts), _dp, C.POINTER(Stats),
+                                   C.c_void_p, C.c_int, C.POINTER(C.c_int)]
+        L.oracle_phipm.restype = C.c_int
+        L.oracle_step.argtypes = [C.c_int, _ip, _ip, _dp, C.c_int, _dp, C.c_double, _dp,
+                                  C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, _dp,
+                                  C.POINTER(C.c_double)]
+        L.oracle_step.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().oracle_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def phi(k: int, z: float) -> float:
+    return lib().oracle_phi(int(k), float(z))
+
+
+def expm(A: np.ndarray) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    E = np.empty_like(A)
+    lib().oracle_expm(A.shape[0], A, E)
+    return E
+
+
+def _csr(A):
+    rp = np.ascontiguousarray(A.indptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+    va = np.ascontiguousarray(A.data, dtype=np.float64)
+    if va.size == 0:
+        va = np.zeros(1)
+        ci = np.zeros(1, dtype=np.int32)
+    return rp, ci, va
+
+
+def spmv(A, x) -> np.ndarray:
+    rp, ci, va = _csr(A)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(A.shape[0])
+    lib().oracle_spmv(A.shape[0], rp, ci, va, x, y)
+    return y
+
+
+def is_symmetric(A) -> bool:
+    rp, ci, va = _csr(A)
+    return bool(lib().oracle_is_symmetric(A.shape[0], rp, ci, va))
+
+
+def krylov(A, v, m: int, lanczos: bool, reorth: int = 1):
+    rp, ci, va = _csr(A)
+    n = A.shape[0]
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    V = np.zeros((m + 1) * n)
+    H = np.zeros((m + 1) * m)
+    beta = C.c_double()
+    mm = lib().oracle_krylov(n, rp, ci, va, v, m, int(lanczos), int(reorth), V, H,
+                             C.byref(beta))
+    return V.reshape(m + 1, n).T.copy(), H.reshape(m + 1, m), beta.value, mm
+
+
+def tau0(tol, anorm, bnorm, m_ave):
+    return lib().oracle_tau0(tol, anorm, bnorm, m_ave)
+
+
+def cost_M(norm1):
+    return lib().oracle_cost_M(norm1)
+
+
+def cost_C1(lanczos, m, p, nnz, n, M):
+    return lib().oracle_cost_C1(int(lanczos), float(m), int(p), float(nnz), float(n), float(M))
+
+
+def cost_C(remaining, tau, C1):
+    return lib().oracle_cost_C(remaining, tau, C1)
+
+
+def alg4(state: Alg4State, tau, m, eps, omega):
+    tn, mn, q, k = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    lib().oracle_alg4(C.byref(state), tau, int(m), eps, omega, C.byref(tn), C.byref(mn),
+                      C.byref(q), C.byref(k))
+    return tn.value, mn.value, q.value, k.value
+
+
+def phipm(t, A, b, opts: Opts | None = None, trace_cap: int = 0, **kw):
+    """u = sum_k t^k phi_k(tA) b_k; b is n x (p+1).  Returns (u, stats[, trace])."""
+    if opts is None:
+        opts = default_opts(**kw)
+    rp, ci, va = _csr(A)
+    n = A.shape[0]
+    b = np.asarray(b, dtype=np.float64)
+    if b.ndim == 1:
+        b = b[:, None]
+    p = b.shape[1] - 1
+    bcm = np.ascontiguousarray(b.T).reshape(-1)
+    u = np.empty(n)
+    st = Stats()
+    tl = C.c_int(0)
+    tr = (TraceRec * trace_cap)() if trace_cap > 0 else None
+    rc = lib().oracle_phipm(float(t), n, rp, ci, va, p, bcm, C.byref(opts), u, C.byref(st),
+                            C.cast(tr, C.c_void_p) if tr is not None else None, trace_cap,
+                            C.byref(tl))
+    if rc != 0:
+        raise RuntimeError(f"oracle_phipm failed with status {rc}")
+    if trace_cap > 0:
+        recs = [{k: getattr(tr[i], k) for k, _ in TraceRec._fields_} for i in range(tl.value)]
+        return u, st.as_dict(), recs
+    return u, st.as_dict()
+
+
+def step(A, b, t_k, u_k, tau, m, lanczos, reorth=1, corrector=1):
+    rp, ci, va = _csr(A)
+    n = A.shape[0]
+    b = np.asarray(b, dtype=np.float64)
+    if b.ndim == 1:
+        b = b[:, None]
+    p = b.shape[1] - 1
+    bcm = np.ascontiguousarray(b.T).reshape(-1)
+    out = np.empty(n)
+    eps = C.c_double()
+    lib().oracle_step(n, rp, ci, va, p, bcm, float(t_k),
+                      np.ascontiguousarray(u_k, dtype=np.float64), float(tau), int(m),
+                      int(lanczos), int(reorth), int(corrector), out, C.byref(eps))
+    return out, eps.value

@@ -1,0 +1,127 @@
+/*
+ * CPU oracle for the adaptive Krylov phi-function solver of Niesen & Wright,
+ * "A Krylov subspace algorithm for evaluating the phi-functions appearing in
+ * exponential integrators" (Algorithms 3 and 4 with eqs. tau_0 ... 8).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This header and its C file are a plain, slow,
+ * double-precision reference used by tests/, the smoke check and the CPU
+ * baseline leg of the benchmark.  The GPU library never includes, links or
+ * calls anything from here, and nothing here includes GPU headers.
+ *
+ * Parity status of each exported function (see the pins under tests/):
+ *   oracle_phi           pinned: closed forms of phi_1..phi_3, phi_k(0)=1/k!,
+ *                        the recurrence (eq. phirelation) and quadrature of
+ *                        the integral definition (eq. phifunctions).
+ *   oracle_expm          pinned: diagonal, nilpotent, rotation closed forms,
+ *                        a library matrix exponential, the augmented-matrix
+ *                        identity of eq. hathm.
+ *   oracle_krylov        pinned: orthonormality, the Arnoldi relation,
+ *                        tridiagonal H for symmetric A, MGS vs CGS2 agreement.
+ *   oracle_phipm         pinned: brute-force exponential of the augmented
+ *                        block matrix (Lemma 2.1 / eq. phide), diagonal A,
+ *                        A = 0, eigenvector decay, stepping and resume
+ *                        identities (eq. steppre), linearity, forward-back.
+ *   oracle_tau0, oracle_cost_*, oracle_alg4
+ *                        pinned by properties (fixed points at omega=gamma,
+ *                        recovery of a known order / decay rate).  The
+ *                        step-by-step trajectory of the controller has no
+ *                        printed worked example: parity unpinned.
+ */
+#ifndef PHIPM_ORACLE_H
+#define PHIPM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Krylov flavours.  Arnoldi: 0 = modified Gram-Schmidt exactly as Algorithm 1,
+ * 1 = classical Gram-Schmidt applied twice (CGS2).  Lanczos: 0 = three-term
+ * recurrence of Algorithm 2 (indices read as the standard recurrence), 1 = CGS2
+ * against the two previous basis vectors only. */
+typedef struct {
+  double  tol;        /* absolute tolerance Tol of eq. taunew (default 1e-7) */
+  int32_t symm;       /* -1 detect exactly, 0 Arnoldi, 1 Lanczos */
+  int32_t m_init;     /* initial Krylov dimension (Algorithm 3: 10) */
+  int32_t m_max;      /* largest Krylov dimension (default 100) */
+  int32_t reorth;     /* 1 = CGS2 flavour (default), 0 = as printed */
+  int32_t adapt_m;    /* 1 = adapt m (phipm), 0 = keep m fixed (phip) */
+  int32_t corrector;  /* 1 = use eq. phipapprox2 (default), 0 = eq. phipapprox */
+  int32_t pad_;
+  double  tau_fixed;  /* > 0: fixed substep, every attempt accepted */
+  int64_t max_attempts;
+} oracle_opts;
+
+typedef struct {
+  int64_t steps, rejected, matvecs, expms;  /* the four counters of stats */
+  double  t_reached, tau_last;
+  int32_t m_last, status;
+} oracle_stats;
+
+/* One record per attempt (accepted or rejected). */
+typedef struct {
+  double  t, tau, eps, omega, beta, hnext, anorm, tau_next;
+  int32_t m, accepted, step, m_next;
+} oracle_trace_rec;
+
+enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_EMAXSTEPS = -5, ORACLE_ENONFINITE = -4 };
+
+void   oracle_default_opts(oracle_opts* o);
+
+/* scalar phi_k(z), k >= 0 */
+double oracle_phi(int k, double z);
+
+/* E = exp(A) for a dense row-major N x N matrix: degree-13 diagonal Pade with
+ * scaling and squaring.  Returns the number of squarings s. */
+int    oracle_expm(int N, const double* A, double* E);
+
+/* y = A x for CSR A */
+void   oracle_spmv(int n, const int32_t* rp, const int32_t* ci, const double* val,
+                   const double* x, double* y);
+
+/* 1 if the CSR matrix equals its transpose entry by entry (bitwise values). */
+int    oracle_is_symmetric(int n, const int32_t* rp, const int32_t* ci, const double* val);
+
+/* Build an m-step Krylov basis of v.  V: n x (m+1) column-major, H: (m+1) x m
+ * row-major.  lanczos/reorth select the flavour.  Returns the number of
+ * columns of H actually produced (< m on breakdown). */
+int    oracle_krylov(int n, const int32_t* rp, const int32_t* ci, const double* val,
+                     const double* v, int m, int lanczos, int reorth,
+                     double* V, double* H, double* beta_out);
+
+/* Controller pieces. */
+double oracle_tau0(double tol, double anorm, double bnorm, double m_ave);
+double oracle_cost_M(double norm1);
+double oracle_cost_C1(int lanczos, double m, int p, double nnz, double n, double M);
+double oracle_cost_C(double remaining, double tau, double C1);
+
+typedef struct {
+  int32_t prev_rejected, prev_branch;   /* branch: 1 = tau changed, 2 = m changed */
+  int32_t q_valid, k_valid;
+  double  q_hat, k_hat, eps_old, tau_old;
+  int32_t m_old, pad_;
+} oracle_alg4_state;
+
+/* Algorithm 4: given the current attempt (tau, m, eps, omega) returns the
+ * proposals tau_new and m_new (eq. 2, eq. 3; m_new rounded up). */
+void   oracle_alg4(oracle_alg4_state* s, double tau, int m, double eps, double omega,
+                   double* tau_new, double* m_new, double* q_used, double* k_used);
+
+/* Full solver: u = phi_0(tA)b_0 + t phi_1(tA)b_1 + ... + t^p phi_p(tA) b_p.
+ * b is n x (p+1) column-major.  trace may be NULL. */
+int    oracle_phipm(double t, int n, const int32_t* rp, const int32_t* ci, const double* val,
+                    int p, const double* b, const oracle_opts* o, double* u,
+                    oracle_stats* st, oracle_trace_rec* trace, int trace_cap, int* trace_len);
+
+/* One step of eq. step with a fixed (tau, m) from state (t_k, u_k).  Returns
+ * the error estimate in *eps. */
+int    oracle_step(int n, const int32_t* rp, const int32_t* ci, const double* val,
+                   int p, const double* b, double t_k, const double* u_k,
+                   double tau, int m, int lanczos, int reorth, int corrector,
+                   double* u_next, double* eps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,665 @@
+/*
+ * CPU oracle for the adaptive Krylov phi-function solver of Niesen & Wright.
+ *
+ * TEST INFRASTRUCTURE ONLY: a plain, slow, obviously-correct double-precision
+ * implementation that the GPU library is checked against.  Only tests/, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code with the GPU path: the two sides meet only through seeded inputs.
+ *
+ * Every function follows the paper's steps in the paper's order.  Readings of
+ * passages that are ambiguous or misprinted are marked "Reading:".  Sparse
+ * products and inner products are OpenMP-parallel over rows; everything else
+ * is straight loops.
+ */
+#include "oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- defaults */
+
+void oracle_default_opts(oracle_opts* o) {
+  memset(o, 0, sizeof(*o));
+  o->tol = 1e-7;          /* Sect. 3.5: default tolerance */
+  o->symm = -1;           /* Sect. 3.5: detect symmetry when A is explicit */
+  o->m_init = 10;         /* Algorithm 3: initial guess m = 10 */
+  o->m_max = 100;         /* Reading: the paper never fixes the maximum */
+  o->reorth = 1;
+  o->adapt_m = 1;
+  o->corrector = 1;
+  o->tau_fixed = 0.0;
+  o->max_attempts = 1000000;
+}
+
+/* ------------------------------------------------------- scalar phi_k(z) */
+
+/* Eq. phifunctions.  Small |z|: the power series phi_k(z) = sum_i z^i/(i+k)!
+ * that follows from the integral.  Otherwise the recurrence eq. phirelation
+ * run upward from phi_0 = e^z: phi_{l+1} = (phi_l - 1/l!) / z. */
+double oracle_phi(int k, double z) {
+  if (fabs(z) < 1.0) {
+    double term = 1.0, sum = 0.0;
+    for (int i = 1; i <= k; ++i) term /= (double)i;       /* 1/k! */
+    for (int i = 0; i < 80; ++i) {
+      sum += term;
+      term *= z / (double)(i + k + 1);
+      if (fabs(term) < 1e-20 * fabs(sum)) break;
+    }
+    return sum;
+  }
+  double ph = exp(z), fact = 1.0;                           /* fact = l! */
+  for (int l = 0; l < k; ++l) {
+    ph = (ph - 1.0 / fact) / z;
+    fact *= (double)(l + 1);
+  }
+  return ph;
+}
+
+/* ------------------------------------------------------ vector primitives */
+
+void oracle_spmv(int n, const int32_t* rp, const int32_t* ci, const double* val,
+                 const double* x, double* y) {
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc += val[k] * x[ci[k]];
+    y[i] = acc;
+  }
+}
+
+static double dot(int n, const double* x, const double* y) {
+  double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
+  for (int i = 0; i < n; ++i) s += x[i] * y[i];
+  return s;
+}
+
+static double norm2(int n, const double* x) { return sqrt(dot(n, x, x)); }
+
+static double norm_inf(int n, const double* x) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s = fmax(s, fabs(x[i]));
+  return s;
+}
+
+static void axpy(int n, double a, const double* x, double* y) {
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) y[i] += a * x[i];
+}
+
+int oracle_is_symmetric(int n, const int32_t* rp, const int32_t* ci, const double* val) {
+  for (int i = 0; i < n; ++i) {
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      int j = ci[k];
+      int found = 0;
+      for (int32_t q = rp[j]; q < rp[j + 1]; ++q) {
+        if (ci[q] == i) { found = (val[q] == val[k]); break; }
+      }
+      if (!found) return 0;
+    }
+  }
+  return 1;
+}
+
+/* --------------------------------------------- dense exponential (Pade-13) */
+
+static void matmul(int N, const double* A, const double* B, double* C) {
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < N; ++k) s += A[i * N + k] * B[k * N + j];
+      C[i * N + j] = s;
+    }
+}
+
+static double norm1_dense(int N, const double* A) {
+  double best = 0.0;
+  for (int j = 0; j < N; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += fabs(A[i * N + j]);
+    best = fmax(best, s);
+  }
+  return best;
+}
+
+/* Solve M X = R (both N x N) by LU with partial pivoting; X overwrites R. */
+static void lu_solve(int N, double* M, double* R) {
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < N; ++i)
+      if (fabs(M[i * N + k]) > fabs(M[piv * N + k])) piv = i;
+    if (piv != k) {
+      for (int j = 0; j < N; ++j) {
+        double t = M[k * N + j]; M[k * N + j] = M[piv * N + j]; M[piv * N + j] = t;
+        t = R[k * N + j]; R[k * N + j] = R[piv * N + j]; R[piv * N + j] = t;
+      }
+    }
+    for (int i = k + 1; i < N; ++i) {
+      double l = M[i * N + k] / M[k * N + k];
+      M[i * N + k] = l;
+      for (int j = k + 1; j < N; ++j) M[i * N + j] -= l * M[k * N + j];
+      for (int j = 0; j < N; ++j) R[i * N + j] -= l * R[k * N + j];
+    }
+  }
+  for (int k = N - 1; k >= 0; --k) {
+    for (int j = 0; j < N; ++j) {
+      double s = R[k * N + j];
+      for (int i = k + 1; i < N; ++i) s -= M[k * N + i] * R[i * N + j];
+      R[k * N + j] = s / M[k * N + k];
+    }
+  }
+}
+
+/* Higham's scaling-and-squaring with the degree-13 diagonal Pade approximant,
+ * as the paper prescribes for exp of the augmented matrix.  Reading: degree
+ * 13 is always used (the paper's cost model eq. 8 assumes it) and the scaling
+ * threshold is the paper's 5.37.  Pade coefficients from their closed form
+ * c_j = (26-j)! 13! / (26! j! (13-j)!). */
+int oracle_expm(int N, const double* A, double* E) {
+  if (N <= 0) return 0;
+  const size_t sz = (size_t)N * N;
+  double* X = (double*)malloc(sz * sizeof(double));
+  double* X2 = (double*)malloc(sz * sizeof(double));
+  double* X4 = (double*)malloc(sz * sizeof(double));
+  double* X6 = (double*)malloc(sz * sizeof(double));
+  double* T = (double*)malloc(sz * sizeof(double));
+  double* U = (double*)malloc(sz * sizeof(double));
+  double* V = (double*)malloc(sz * sizeof(double));
+
+  double c[14];
+  c[0] = 1.0;
+  for (int j = 0; j < 13; ++j) c[j + 1] = c[j] * (double)(13 - j) / ((double)(j + 1) * (double)(26 - j));
+
+  double nrm = norm1_dense(N, A);
+  int s = 0;
+  if (nrm > 5.37) s = (int)ceil(log2(nrm / 5.37));
+  if (s < 0) s = 0;
+  double scale = ldexp(1.0, -s);
+  for (size_t i = 0; i < sz; ++i) X[i] = A[i] * scale;
+
+  matmul(N, X, X, X2);
+  matmul(N, X2, X2, X4);
+  matmul(N, X4, X2, X6);
+
+  /* U = X [ X6 (c13 X6 + c11 X4 + c9 X2) + c7 X6 + c5 X4 + c3 X2 + c1 I ] */
+  for (size_t i = 0; i < sz; ++i) T[i] = c[13] * X6[i] + c[11] * X4[i] + c[9] * X2[i];
+  matmul(N, X6, T, U);
+  for (size_t i = 0; i < sz; ++i) U[i] += c[7] * X6[i] + c[5] * X4[i] + c[3] * X2[i];
+  for (int i = 0; i < N; ++i) U[i * N + i] += c[1];
+  matmul(N, X, U, T);
+  memcpy(U, T, sz * sizeof(double));
+
+  /* V = X6 (c12 X6 + c10 X4 + c8 X2) + c6 X6 + c4 X4 + c2 X2 + c0 I */
+  for (size_t i = 0; i < sz; ++i) T[i] = c[12] * X6[i] + c[10] * X4[i] + c[8] * X2[i];
+  matmul(N, X6, T, V);
+  for (size_t i = 0; i < sz; ++i) V[i] += c[6] * X6[i] + c[4] * X4[i] + c[2] * X2[i];
+  for (int i = 0; i < N; ++i) V[i * N + i] += c[0];
+
+  /* (V - U) R = (V + U) */
+  for (size_t i = 0; i < sz; ++i) { T[i] = V[i] - U[i]; E[i] = V[i] + U[i]; }
+  lu_solve(N, T, E);
+
+  for (int k = 0; k < s; ++k) {
+    matmul(N, E, E, T);
+    memcpy(E, T, sz * sizeof(double));
+  }
+  free(X); free(X2); free(X4); free(X6); free(T); free(U); free(V);
+  return s;
+}
+
+/* --------------------------------------------------------- Krylov bases */
+
+/* One step j (0-based) of the chosen flavour: given v_0..v_j in V (columns of
+ * length n), fills column j of H (row-major, ldh columns) and v_{j+1}.
+ * Returns h_{j+1,j}.  w is scratch of length n. */
+static double krylov_step(int n, const int32_t* rp, const int32_t* ci, const double* val,
+                          double* V, double* H, int ldh, int j, int lanczos, int reorth,
+                          double* w) {
+  const double* vj = V + (size_t)j * n;
+  oracle_spmv(n, rp, ci, val, vj, w);
+  if (!lanczos && !reorth) {
+    /* Algorithm 1 as printed: modified Gram-Schmidt */
+    for (int i = 0; i <= j; ++i) {
+      double h = dot(n, V + (size_t)i * n, w);
+      H[i * ldh + j] = h;
+      axpy(n, -h, V + (size_t)i * n, w);
+    }
+  } else if (lanczos && !reorth) {
+    /* Algorithm 2.  Reading: the standard three-term recurrence; the printed
+     * indices of the off-diagonal entries are garbled. */
+    double a = dot(n, vj, w);
+    H[j * ldh + j] = a;
+    if (j > 0) {
+      double bprev = H[j * ldh + (j - 1)];
+      H[(j - 1) * ldh + j] = bprev;
+      axpy(n, -bprev, V + (size_t)(j - 1) * n, w);
+    }
+    axpy(n, -a, vj, w);
+  } else {
+    /* CGS2: classical Gram-Schmidt twice.  Lanczos restricts the projection
+     * to the two most recent basis vectors. */
+    int i0 = lanczos ? (j > 0 ? j - 1 : 0) : 0;
+    double c[1024];
+    for (int i = i0; i <= j; ++i) H[i * ldh + j] = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = i0; i <= j; ++i) c[i - i0] = dot(n, V + (size_t)i * n, w);
+      for (int i = i0; i <= j; ++i) {
+        axpy(n, -c[i - i0], V + (size_t)i * n, w);
+        H[i * ldh + j] += c[i - i0];
+      }
+    }
+  }
+  double h = norm2(n, w);
+  H[(j + 1) * ldh + j] = h;
+  double* vn = V + (size_t)(j + 1) * n;
+  if (h > 0.0)
+    for (int i = 0; i < n; ++i) vn[i] = w[i] / h;
+  else
+    for (int i = 0; i < n; ++i) vn[i] = 0.0;
+  return h;
+}
+
+int oracle_krylov(int n, const int32_t* rp, const int32_t* ci, const double* val,
+                  const double* v, int m, int lanczos, int reorth,
+                  double* V, double* H, double* beta_out) {
+  double beta = norm2(n, v);
+  *beta_out = beta;
+  memset(H, 0, sizeof(double) * (size_t)(m + 1) * m);
+  for (int i = 0; i < n; ++i) V[i] = v[i] / beta;
+  double* w = (double*)malloc(sizeof(double) * n);
+  int j = 0;
+  for (; j < m; ++j) {
+    double h = krylov_step(n, rp, ci, val, V, H, m, j, lanczos, reorth, w);
+    if (h == 0.0) { ++j; break; }
+  }
+  free(w);
+  return j;
+}
+
+/* ----------------------------------------------------- controller pieces */
+
+/* Eq. tau_0: the Expokit initial step, enlarged by a factor 10. */
+double oracle_tau0(double tol, double anorm, double bnorm, double m_ave) {
+  const double mp1 = m_ave + 1.0;
+  double inner = tol * pow(mp1 / exp(1.0), mp1) * sqrt(2.0 * M_PI * mp1) / (4.0 * anorm * bnorm);
+  return 10.0 / anorm * pow(inner, 1.0 / m_ave);
+}
+
+/* Eq. 8: M(A) = 44/3 + 2 ceil_+(log2(||A||_1 / 5.37)).  Reading: ceil_+ is
+ * max(0, ceil(.)), the number of squarings of the Pade method. */
+double oracle_cost_M(double norm1) {
+  double s = 0.0;
+  if (norm1 > 5.37) s = ceil(log2(norm1 / 5.37));
+  if (s < 0.0) s = 0.0;
+  return 44.0 / 3.0 + 2.0 * s;
+}
+
+/* Eq. 4: cost of one step with Krylov dimension m. */
+double oracle_cost_C1(int lanczos, double m, int p, double nnz, double n, double M) {
+  double mp = m + (double)p;
+  double e = M * pow(mp + 1.0, 3.0);
+  if (lanczos) return mp * nnz + 3.0 * mp * n + e;
+  return mp * nnz + (m * m + 3.0 * p + 2.0) * n + e;
+}
+
+/* Eq. 5: C(tau, m) = ceil((t_end - t_k)/tau) C_1(m).  Reading: at least one
+ * step is always needed, so the count is at least 1. */
+double oracle_cost_C(double remaining, double tau, double C1) {
+  double k = ceil(remaining / tau);
+  if (!(k >= 1.0)) k = 1.0;
+  return k * C1;
+}
+
+/* Algorithm 4.  Readings: "previous step" is the previous attempt within the
+ * same time step; eq. 6 is used with its ratio the right way up
+ * (q = log(eps/eps_old)/log(tau/tau_old) - 1, matching error ~ tau^(q+1));
+ * "m was reduced" is read as "m was changed" (after a rejection m can only
+ * grow).  Non-finite or non-positive estimates fall back to the defaults. */
+void oracle_alg4(oracle_alg4_state* s, double tau, int m, double eps, double omega,
+                 double* tau_new, double* m_new, double* q_used, double* k_used) {
+  const double gamma = 0.8;
+  double q;
+  if (s->prev_rejected && s->prev_branch == 1) {
+    q = log(eps / s->eps_old) / log(tau / s->tau_old) - 1.0;
+    if (isfinite(q) && q > 0.0) s->q_valid = 1; else { q = 0.25 * m; s->q_valid = 0; }
+    s->q_hat = q;
+  } else if (s->prev_rejected && s->q_valid) {
+    q = s->q_hat;
+  } else {
+    q = 0.25 * m;
+    s->q_valid = 0;
+    s->q_hat = q;
+  }
+  *tau_new = tau * pow(gamma / omega, 1.0 / (q + 1.0));
+
+  double kap;
+  if (s->prev_rejected && s->prev_branch == 2) {
+    kap = pow(eps / s->eps_old, 1.0 / (double)(s->m_old - m));
+    if (isfinite(kap) && kap > 1.0) s->k_valid = 1; else { kap = 2.0; s->k_valid = 0; }
+    s->k_hat = kap;
+  } else if (s->prev_rejected && s->k_valid) {
+    kap = s->k_hat;
+  } else {
+    kap = 2.0;
+    s->k_valid = 0;
+    s->k_hat = kap;
+  }
+  /* Eq. 3, rounded up to the smallest integer dimension that meets it. */
+  *m_new = ceil((double)m + log(omega / gamma) / log(kap));
+  if (q_used) *q_used = q;
+  if (k_used) *k_used = kap;
+}
+
+/* ------------------------------------------------------------ the solver */
+
+static double fact(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= (double)i;
+  return f;
+}
+
+typedef struct {
+  int n, nnz;
+  const int32_t* rp;
+  const int32_t* ci;
+  const double* val;
+} csr_t;
+
+/* Eq. wrecurrence: w_0 = u_k, w_j = A w_{j-1} + sum_{l=0}^{p-j} t_k^l/l! b_{j+l}. */
+static void w_recurrence(const csr_t* A, int p, const double* b, double tk,
+                         const double* uk, double* W) {
+  const int n = A->n;
+  memcpy(W, uk, sizeof(double) * n);
+  for (int j = 1; j <= p; ++j) {
+    double* wj = W + (size_t)j * n;
+    oracle_spmv(n, A->rp, A->ci, A->val, W + (size_t)(j - 1) * n, wj);
+    for (int l = 0; l <= p - j; ++l)
+      axpy(n, pow(tk, l) / fact(l), b + (size_t)(j + l) * n, wj);
+  }
+}
+
+/* exp of the augmented matrix tau*K, K = [[H_m, e_1, 0], [0, 0, I_p], [0, 0, 0]]
+ * of size m+p+1 (eq. hathm with one extra row/column so that phi_{p+1} needed
+ * by the corrector eq. phipapprox2 appears too).  Column m+k-1 (0-based) of
+ * exp(tau K) holds tau^k phi_k(tau H_m) e_1 in its top m rows; column 0
+ * holds exp(tau H_m) e_1.  Outputs y = tau^p phi_p(tau H) e_1 (m entries) and
+ * c = [tau^{p+1} phi_{p+1}(tau H)]_{m,1}.  Returns norm_1(tau K). */
+static double augmented_expm(const double* H, int ldh, int m, int p, double tau,
+                             double* y, double* c) {
+  const int N = m + p + 1;
+  double* K = (double*)calloc((size_t)N * N, sizeof(double));
+  double* E = (double*)malloc(sizeof(double) * (size_t)N * N);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) K[i * N + j] = tau * H[i * ldh + j];
+  K[0 * N + m] = tau;
+  for (int i = 0; i < p; ++i) K[(m + i) * N + (m + i + 1)] = tau;
+  double nrm = norm1_dense(N, K);
+  oracle_expm(N, K, E);
+  int col = (p == 0) ? 0 : (m + p - 1);
+  for (int i = 0; i < m; ++i) y[i] = E[i * N + col];
+  *c = E[(m - 1) * N + (m + p)];
+  free(K);
+  free(E);
+  return nrm;
+}
+
+int oracle_step(int n, const int32_t* rp, const int32_t* ci, const double* val,
+                int p, const double* b, double t_k, const double* u_k,
+                double tau, int m, int lanczos, int reorth, int corrector,
+                double* u_next, double* eps) {
+  csr_t A = {n, rp[n], rp, ci, val};
+  double* W = (double*)malloc(sizeof(double) * (size_t)n * (p + 1));
+  w_recurrence(&A, p, b, t_k, u_k, W);
+  const double* wp = W + (size_t)p * n;
+  double beta = norm2(n, wp);
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < p; ++j) s += pow(tau, j) / fact(j) * W[(size_t)j * n + i];
+    u_next[i] = s;
+  }
+  *eps = 0.0;
+  if (beta > 0.0) {
+    double* V = (double*)malloc(sizeof(double) * (size_t)n * (m + 1));
+    double* H = (double*)malloc(sizeof(double) * (size_t)(m + 1) * m);
+    double bdummy;
+    int mm = oracle_krylov(n, rp, ci, val, wp, m, lanczos, reorth, V, H, &bdummy);
+    double hnext = H[mm * m + (mm - 1)];
+    double* y = (double*)malloc(sizeof(double) * mm);
+    double c;
+    /* H_mm sits in the leading block of the (m+1) x m array */
+    augmented_expm(H, m, mm, p, tau, y, &c);
+    for (int k = 0; k < mm; ++k) axpy(n, beta * y[k], V + (size_t)k * n, u_next);
+    if (corrector) axpy(n, beta * hnext * c, V + (size_t)mm * n, u_next);
+    *eps = beta * fabs(hnext) * fabs(c);
+    free(y); free(V); free(H);
+  }
+  free(W);
+  return 0;
+}
+
+static double csr_norm_inf(const csr_t* A) {
+  double best = 0.0;
+  for (int i = 0; i < A->n; ++i) {
+    double s = 0.0;
+    for (int32_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s += fabs(A->val[k]);
+    best = fmax(best, s);
+  }
+  return best;
+}
+
+/* Algorithm 3 with Algorithm 4. */
+int oracle_phipm(double t_end, int n, const int32_t* rp, const int32_t* ci, const double* val_in,
+                 int p, const double* b_in, const oracle_opts* o, double* u,
+                 oracle_stats* st, oracle_trace_rec* trace, int trace_cap, int* trace_len) {
+  const double delta = 1.2;
+  oracle_stats stats;
+  memset(&stats, 0, sizeof(stats));
+  if (trace_len) *trace_len = 0;
+  if (n <= 0 || p < 0 || !(o->tol > 0.0) || !isfinite(t_end) || o->m_init < 1 ||
+      o->m_max < o->m_init || o->m_max > 1000) {
+    stats.status = ORACLE_EINVAL;
+    if (st) *st = stats;
+    return ORACLE_EINVAL;
+  }
+  const int nnz = rp[n];
+
+  /* t_end = 0: u = b_0. */
+  if (t_end == 0.0) {
+    memcpy(u, b_in, sizeof(double) * n);
+    if (st) *st = stats;
+    return ORACLE_OK;
+  }
+
+  /* Reading: a negative end time integrates the ODE with -A and b_k scaled by
+   * (-1)^k over |t_end|, which gives the same linear combination. */
+  const double sgn = t_end < 0.0 ? -1.0 : 1.0;
+  t_end = fabs(t_end);
+  double* val = (double*)malloc(sizeof(double) * (nnz > 0 ? nnz : 1));
+  for (int k = 0; k < nnz; ++k) val[k] = sgn * val_in[k];
+  double* b = (double*)malloc(sizeof(double) * (size_t)n * (p + 1));
+  for (int k = 0; k <= p; ++k) {
+    double f = (sgn < 0.0 && (k & 1)) ? -1.0 : 1.0;
+    for (int i = 0; i < n; ++i) b[(size_t)k * n + i] = f * b_in[(size_t)k * n + i];
+  }
+  csr_t A = {n, nnz, rp, ci, val};
+
+  const double anorm = csr_norm_inf(&A);
+  double bnorm = norm_inf(n, b);
+  for (int k = 1; k <= p && bnorm == 0.0; ++k) bnorm = fmax(bnorm, norm_inf(n, b + (size_t)k * n));
+
+  int status = ORACLE_OK;
+  if (anorm == 0.0 || bnorm == 0.0) {
+    /* A = 0: phi_k(0) = 1/k!, so u = sum_k t^k/k! b_k (also covers b = 0). */
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int k = 0; k <= p; ++k) s += pow(t_end, k) / fact(k) * b[(size_t)k * n + i];
+      u[i] = s;
+    }
+    stats.t_reached = t_end;
+    goto done;
+  }
+
+  {
+    int lanczos;
+    if (o->symm < 0) lanczos = oracle_is_symmetric(n, rp, ci, val);
+    else lanczos = o->symm ? 1 : 0;
+    const int m_cap = o->m_max < n ? o->m_max : n;
+
+    double tau;
+    if (o->tau_fixed > 0.0) tau = o->tau_fixed;
+    else tau = oracle_tau0(o->tol, anorm, bnorm, 0.5 * (double)(o->m_init + o->m_max));
+    if (!(tau > 0.0) || !isfinite(tau)) tau = t_end;  /* Reading: degenerate tau_0 */
+    if (tau > t_end) tau = t_end;
+    int m = o->m_init < m_cap ? o->m_init : m_cap;
+
+    double* W = (double*)malloc(sizeof(double) * (size_t)n * (p + 1));
+    double* V = (double*)malloc(sizeof(double) * (size_t)n * (m_cap + 1));
+    double* H = (double*)malloc(sizeof(double) * (size_t)(m_cap + 1) * m_cap);
+    double* wtmp = (double*)malloc(sizeof(double) * n);
+    double* y = (double*)malloc(sizeof(double) * (m_cap + 1));
+    const double bd_tol = ldexp(anorm, -40);  /* Reading: happy-breakdown level */
+
+    double t = 0.0;
+    memcpy(u, b, sizeof(double) * n);
+    int64_t attempts = 0;
+
+    while (t < t_end) {
+      if (tau > t_end - t) tau = t_end - t;
+      w_recurrence(&A, p, b, t, u, W);
+      stats.matvecs += p;
+      const double* wp = W + (size_t)p * n;
+      const double beta = norm2(n, wp);
+      if (!isfinite(beta)) { status = ORACLE_ENONFINITE; break; }
+
+      int have = 0;          /* basis vectors v_0..v_have built: H has `have` columns */
+      int broke = 0;         /* happy breakdown after `have` columns */
+      if (beta > 0.0)
+        for (int i = 0; i < n; ++i) V[i] = wp[i] / beta;
+      memset(H, 0, sizeof(double) * (size_t)(m_cap + 1) * m_cap);
+
+      oracle_alg4_state as;
+      memset(&as, 0, sizeof(as));
+      for (;;) {
+        if (++attempts > o->max_attempts) { status = ORACLE_EMAXSTEPS; break; }
+        double eps = 0.0, hnext = 0.0, c = 0.0, knorm = 0.0;
+        int m_use = m;
+        if (beta > 0.0) {
+          while (!broke && have < m) {
+            double h = krylov_step(n, rp, ci, val, V, H, m_cap, have, lanczos, o->reorth, wtmp);
+            stats.matvecs += 1;
+            ++have;
+            if (h <= bd_tol || have == n) broke = 1;
+          }
+          if (broke && have < m_use) m_use = have;
+          if (broke) {
+            /* Invariant subspace: the projection is exact for any tau. */
+            hnext = 0.0;
+            if (o->tau_fixed <= 0.0) tau = t_end - t;
+          } else {
+            hnext = H[m_use * m_cap + (m_use - 1)];
+          }
+          knorm = augmented_expm(H, m_cap, m_use, p, tau, y, &c);
+          stats.expms += 1;
+          eps = beta * fabs(hnext) * fabs(c);   /* eq. errest */
+        }
+        const double omega = t_end * eps / (tau * o->tol);   /* eq. taunew */
+
+        int accept;
+        double tau_next = tau;
+        int m_next = m;
+        if (o->tau_fixed > 0.0) {
+          accept = 1;
+        } else if (!isfinite(omega)) {
+          /* Reading: a non-finite estimate rejects and shrinks tau by 5. */
+          accept = 0;
+          tau_next = tau / 5.0;
+          as.prev_rejected = 0;
+        } else {
+          double tau_new, m_new;
+          oracle_alg4(&as, tau, m_use, eps, omega, &tau_new, &m_new, NULL, NULL);
+          const double M = oracle_cost_M(knorm);
+          const double rem = t_end - t;
+          double m_cost = m_new < 1.0 ? 1.0 : m_new;  /* Reading: dimension >= 1 */
+          double c_tau = oracle_cost_C(rem, tau_new, oracle_cost_C1(lanczos, m_use, p, nnz, n, M));
+          double c_m = oracle_cost_C(rem, tau, oracle_cost_C1(lanczos, m_cost, p, nnz, n, M));
+          accept = omega <= delta;
+          int branch;
+          int m_cand = m;
+          if (o->adapt_m && !broke) {
+            double mm = m_new;
+            double lo = floor(0.75 * m_use);
+            if (mm < lo) mm = lo;
+            if (mm < 1.0) mm = 1.0;
+            double hi = ceil(4.0 * m_use / 3.0);
+            if (mm > hi) mm = hi;
+            if (mm > m_cap) mm = m_cap;
+            m_cand = (int)mm;
+          }
+          /* Reading: the m-branch is taken when it is not dearer; if m cannot
+           * move (fixed m, cap reached, breakdown) while rejecting, adapt tau. */
+          if (c_tau < c_m || !o->adapt_m || broke || (!accept && m_cand <= m_use)) branch = 1;
+          else branch = 2;
+          if (branch == 1) {
+            double tn = tau_new;
+            if (tn < tau / 5.0) tn = tau / 5.0;
+            if (tn > 2.0 * tau) tn = 2.0 * tau;
+            if (tn > rem) tn = rem;
+            tau_next = tn;
+            m_next = m_use;
+          } else {
+            m_next = m_cand;
+          }
+          as.prev_branch = branch;
+          as.eps_old = eps;
+          as.tau_old = tau;
+          as.m_old = m_use;
+          as.prev_rejected = !accept;
+        }
+
+        if (trace && trace_len && *trace_len < trace_cap) {
+          oracle_trace_rec* r = &trace[(*trace_len)++];
+          r->t = t; r->tau = tau; r->eps = eps; r->omega = omega; r->beta = beta;
+          r->hnext = hnext; r->anorm = anorm; r->tau_next = tau_next;
+          r->m = m_use; r->accepted = accept; r->step = (int)stats.steps; r->m_next = m_next;
+        }
+
+        if (accept) {
+          /* eq. step with the corrected approximation eq. phipapprox2 */
+          for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < p; ++j) s += pow(tau, j) / fact(j) * W[(size_t)j * n + i];
+            u[i] = s;
+          }
+          if (beta > 0.0) {
+            for (int k = 0; k < m_use; ++k) axpy(n, beta * y[k], V + (size_t)k * n, u);
+            if (o->corrector && hnext != 0.0)
+              axpy(n, beta * hnext * c, V + (size_t)m_use * n, u);
+          }
+          t += tau;
+          if (t_end - t <= 4.0 * DBL_EPSILON * t_end) t = t_end;
+          stats.steps += 1;
+          stats.tau_last = tau;
+          stats.m_last = m_use;
+          tau = tau_next;
+          m = m_next;
+          break;
+        }
+        stats.rejected += 1;
+        tau = tau_next;
+        m = m_next;
+      }
+      if (status != ORACLE_OK) break;
+    }
+    stats.t_reached = sgn * t;
+    free(W); free(V); free(H); free(wtmp); free(y);
+  }
+
+done:
+  stats.status = status;
+  if (st) *st = stats;
+  free(val);
+  free(b);
+  return status;
+}
