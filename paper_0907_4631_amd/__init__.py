@@ -1,0 +1,222 @@
+"""phipm on MI355X: Python binding of the C ABI in ``include/phipm.h``.
+
+Argument marshalling only: torch tensors supply device memory and the stream;
+every step of the computation runs in the HIP library ``libphipm.so``.  The
+binding raises if that library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphipm.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EMAXSTEPS, EUNSUPPORTED, EABORT = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, FP32_BASIS = 0, 1
+M_CAP, P_MAX = 128, 8
+
+
+class PhipmError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = status_string(status) if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+class CSR(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("symm", C.c_int32), ("m_init", C.c_int32),
+                ("m_max", C.c_int32), ("precision", C.c_int32), ("adapt_m", C.c_int32),
+                ("corrector", C.c_int32), ("tau_fixed", C.c_double),
+                ("max_attempts", C.c_int64), ("workgroups", C.c_int32),
+                ("validate", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("rejected", C.c_int64), ("matvecs", C.c_int64),
+                ("expms", C.c_int64), ("t_reached", C.c_double), ("tau_last", C.c_double),
+                ("m_last", C.c_int32), ("status", C.c_int32), ("lanczos", C.c_int32),
+                ("workgroups", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = ["phipm_default_opts", "phipm_workspace_bytes", "phipm", "phipm_last_status",
+           "phipm_spmv", "phipm_expm", "phipm_krylov", "phipm_status_string"]
+
+
+def lib():
+    """Load libphipm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.phipm_default_opts.argtypes = [C.POINTER(Opts)]
+        L.phipm_default_opts.restype = None
+        L.phipm_workspace_bytes.argtypes = [C.POINTER(CSR), C.c_int, C.POINTER(Opts),
+                                            C.POINTER(C.c_size_t)]
+        L.phipm_workspace_bytes.restype = C.c_int
+        L.phipm.argtypes = [C.c_double, C.POINTER(CSR), C.c_int, vp, C.POINTER(Opts), vp, vp,
+                            C.c_size_t, C.POINTER(Stats), vp]
+        L.phipm.restype = C.c_int
+        L.phipm_last_status.argtypes = []
+        L.phipm_last_status.restype = C.c_int
+        L.phipm_spmv.argtypes = [C.POINTER(CSR), vp, vp, vp]
+        L.phipm_spmv.restype = C.c_int
+        L.phipm_expm.argtypes = [C.c_int, vp, vp, vp, vp]
+        L.phipm_expm.restype = C.c_int
+        L.phipm_krylov.argtypes = [C.POINTER(CSR), vp, C.c_int, C.c_int, vp, vp, vp, C.c_size_t,
+                                   C.POINTER(C.c_int), vp]
+        L.phipm_krylov.restype = C.c_int
+        L.phipm_status_string.argtypes = [C.c_int]
+        L.phipm_status_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().phipm_status_string(int(status)).decode()
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().phipm_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class DeviceCSR:
+    """A CSR matrix resident on the GPU (int32 indices, float64 values)."""
+
+    def __init__(self, A, device="cuda"):
+        torch = _torch()
+        self.n = int(A.shape[0])
+        self.nnz = int(A.nnz)
+        self.row_ptr = torch.as_tensor(np.asarray(A.indptr, dtype=np.int32), device=device)
+        self.col_idx = torch.as_tensor(np.asarray(A.indices, dtype=np.int32), device=device)
+        self.val = torch.as_tensor(np.asarray(A.data, dtype=np.float64), device=device)
+        if self.nnz == 0:   # keep non-null pointers
+            self.col_idx = torch.zeros(1, dtype=torch.int32, device=device)
+            self.val = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def c(self) -> CSR:
+        return CSR(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                   self.val.data_ptr())
+
+
+def workspace_bytes(A: DeviceCSR, p: int, opts: Opts) -> int:
+    nb = C.c_size_t()
+    rc = lib().phipm_workspace_bytes(C.byref(A.c()), int(p), C.byref(opts), C.byref(nb))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_workspace_bytes")
+    return nb.value
+
+
+def alloc_workspace(nbytes: int, device="cuda"):
+    torch = _torch()
+    return torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+
+
+def _aligned(ws):
+    ptr = ws.data_ptr()
+    return (ptr + 255) & ~255
+
+
+class Solver:
+    """Reusable solver: owns a workspace sized for (A, p, opts)."""
+
+    def __init__(self, A: DeviceCSR, p: int, opts: Opts | None = None, **kw):
+        self.A = A
+        self.p = int(p)
+        self.opts = opts if opts is not None else default_opts(**kw)
+        self.ws_bytes = workspace_bytes(A, self.p, self.opts)
+        self.ws = alloc_workspace(self.ws_bytes, device=A.row_ptr.device)
+        self.csr = A.c()
+
+    def __call__(self, t, b, u, stats: bool = True, stream=None):
+        """u <- sum_k t^k phi_k(tA) b_k.  b: (p+1, n) float64 tensor, rows = b_k."""
+        torch = _torch()
+        assert b.dtype == torch.float64 and u.dtype == torch.float64
+        assert b.is_contiguous() and b.shape == (self.p + 1, self.A.n) and u.numel() == self.A.n
+        st = Stats()
+        rc = lib().phipm(float(t), C.byref(self.csr), self.p, C.c_void_p(b.data_ptr()),
+                         C.byref(self.opts), C.c_void_p(u.data_ptr()),
+                         C.c_void_p(_aligned(self.ws)), self.ws_bytes,
+                         C.byref(st) if stats else None, _stream_ptr(stream))
+        if rc != OK:
+            raise PhipmError(rc, "phipm")
+        return st.as_dict() if stats else None
+
+
+def solve(t, A: DeviceCSR, b, opts: Opts | None = None, **kw):
+    """One-shot u = sum_k t^k phi_k(tA) b_k for b given as (p+1, n) tensor."""
+    torch = _torch()
+    p = b.shape[0] - 1
+    s = Solver(A, p, opts, **kw)
+    u = torch.empty(A.n, dtype=torch.float64, device=b.device)
+    st = s(t, b, u)
+    return u, st
+
+
+def spmv(A: DeviceCSR, x, y, stream=None):
+    rc = lib().phipm_spmv(C.byref(A.c()), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                          _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_spmv")
+
+
+def expm(H, stream=None):
+    """exp(H) of a square float64 device tensor with the solver's small exponential."""
+    torch = _torch()
+    N = H.shape[0]
+    H = H.contiguous()
+    E = torch.empty_like(H)
+    S = torch.empty(8 * N * N, dtype=torch.float64, device=H.device)
+    rc = lib().phipm_expm(N, C.c_void_p(H.data_ptr()), C.c_void_p(E.data_ptr()),
+                          C.c_void_p(S.data_ptr()), _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_expm")
+    return E
+
+
+def krylov(A: DeviceCSR, v, m: int, lanczos: bool, stream=None):
+    """m steps of the solver's Krylov process from v.  Returns (V n x (m+1), H (m+1) x m, done)."""
+    torch = _torch()
+    opts = default_opts(m_max=max(m, 10), m_init=1)
+    nb = workspace_bytes(A, 0, opts)
+    ws = alloc_workspace(nb, device=v.device)
+    V = torch.zeros((m + 1) * A.n, dtype=torch.float64, device=v.device)
+    H = torch.zeros((m + 1) * m, dtype=torch.float64, device=v.device)
+    done = C.c_int()
+    rc = lib().phipm_krylov(C.byref(A.c()), C.c_void_p(v.data_ptr()), int(m), int(lanczos),
+                            C.c_void_p(V.data_ptr()), C.c_void_p(H.data_ptr()),
+                            C.c_void_p(_aligned(ws)), nb, C.byref(done), _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_krylov")
+    return V.view(m + 1, A.n).T, H.view(m + 1, m), done.value

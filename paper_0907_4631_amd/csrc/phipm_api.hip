@@ -1,0 +1,418 @@
+// C ABI of the phipm library: argument checks, workspace layout, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/phipm.h"
+#include "solver.hpp"
+
+using namespace pkr;
+
+namespace {
+
+// ------------------------------------------------------------ kernels
+
+__global__ void k_zero_ctl(TeamCtl* ctl, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    ctl[i].count = 0u;
+    ctl[i].gen = 0u;
+    ctl[i].abort = 0u;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_solve(Problem P, Work<T> w, TeamCtl* ctl,
+                                                 double* partials, double* result,
+                                                 unsigned long long spin) {
+  __shared__ Shared sh;
+  Team tm{(int)blockIdx.x, (int)gridDim.x, ctl, partials, result, spin};
+  solve<T>(tm, P, w, sh);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_spmv(int n, const int* rp, const int* ci,
+                                                const double* val, const double* x, double* y) {
+  __shared__ SpmvSmem<double> sm;
+  auto ld = [&](int c) -> double { return x[c]; };
+  for (long long r0 = (long long)blockIdx.x * BLOCK; r0 < n; r0 += (long long)gridDim.x * BLOCK) {
+    const int r1 = (int)std::min<long long>(r0 + BLOCK, n);
+    double acc = spmv_tile<double, double>(rp, ci, val, (int)r0, r1, sm, ld);
+    const int r = (int)r0 + threadIdx.x;
+    if (r < r1) y[r] = acc;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_expm(int N, const double* H, double* E, double* S) {
+  __shared__ double s_norm;
+  __shared__ int s_sq;
+  for (int e = threadIdx.x; e < N * N; e += BLOCK) S[e] = H[e];
+  __syncthreads();
+  const double* R = wg_expm(N, S, &s_norm, &s_sq);
+  for (int e = threadIdx.x; e < N * N; e += BLOCK) E[e] = R[e];
+}
+
+// m Krylov steps from v with the solver's step routine (float64).
+__global__ __launch_bounds__(BLOCK) void k_krylov(Problem P, Work<double> w, const double* v,
+                                                  int m, int lanczos, double* Hout,
+                                                  int* m_done, TeamCtl* ctl, double* partials,
+                                                  double* result, unsigned long long spin) {
+  __shared__ Shared sh;
+  Team tm{(int)blockIdx.x, (int)gridDim.x, ctl, partials, result, spin};
+  int rb, re;
+  own_rows(tm, P.n, rb, re);
+  double a = 0.0;
+  for (int r = rb + threadIdx.x; r < re; r += BLOCK) a += v[r] * v[r];
+  double a1[1] = {a};
+  block_reduce<1>(a1, RED_SUM, sh.blk);
+  if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+  const double beta = sqrt(sh.red[0]);
+  int have = 0;
+  double h = beta;
+  while (have < m) {
+    if (have == 0)
+      h = krylov_step<double, double>(tm, P, w, P.val, 1.0, lanczos != 0, 0, v, 1.0 / beta, rb,
+                                      re, sh);
+    else
+      h = krylov_step<double, double>(tm, P, w, P.val, 1.0, lanczos != 0, have,
+                                      (have - 1) & 1 ? w.y1 : w.y0, 1.0 / h, rb, re, sh);
+    if (h < 0.0) return;
+    ++have;
+    if (h == 0.0) break;
+  }
+  if (h > 0.0) {
+    const double* ys = (have - 1) & 1 ? w.y1 : w.y0;
+    const double sc = 1.0 / h;
+    double* vh = w.V + (long long)have * w.ldv;
+    for (int r = rb + threadIdx.x; r < re; r += BLOCK) vh[r] = ys[r] * sc;
+  }
+  if (tm.rank == 0) {
+    for (int e = threadIdx.x; e < (m + 1) * m; e += BLOCK) {
+      const int i = e / m, j = e - i * m;
+      Hout[e] = j < have ? w.H[(long long)i * M_CAP + j] : 0.0;
+    }
+    if (threadIdx.x == 0) *m_done = have;
+  }
+}
+
+// ----------------------------------------------------------- host side
+
+struct DeviceInfo {
+  int cus = 0;
+  int coresident64 = 0;  // cooperative grid limit for the float64 solver
+  int coresident32 = 0;
+  unsigned long long spin_ticks = 0;
+  bool ok = false;
+};
+
+DeviceInfo g_dev[64];
+std::mutex g_mu;
+
+const DeviceInfo* device_info() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceInfo& d = g_dev[dev];
+  if (!d.ok) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return nullptr;
+    d.cus = prop.multiProcessorCount;
+    int b64 = 0, b32 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b64, k_solve<double>, BLOCK, 0) != hipSuccess)
+      return nullptr;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, k_solve<float>, BLOCK, 0) != hipSuccess)
+      return nullptr;
+    d.coresident64 = std::max(1, b64) * d.cus;
+    d.coresident32 = std::max(1, b32) * d.cus;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      khz = 100000;
+    d.spin_ticks = (unsigned long long)khz * 1000ull * 20ull;  // 20 s per wait
+    d.ok = true;
+  }
+  return &d;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline long long pad64(long long x) { return (x + 63) / 64 * 64; }
+
+struct Layout {
+  long long ldw, ldv;
+  size_t W, V, y0, y1, val32, H, ex, st, stats, ctl, part, res, total;
+};
+
+Layout layout(int n, int nnz, int p, int m_cap, bool fp32, int gmax) {
+  Layout L{};
+  const size_t tb = fp32 ? 4 : 8;
+  L.ldw = pad64(n);
+  L.ldv = pad64(n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  L.W = take(sizeof(double) * (size_t)L.ldw * (size_t)std::max(p, 1));
+  L.V = take(tb * (size_t)L.ldv * (size_t)(m_cap + 1));
+  L.y0 = take(tb * (size_t)L.ldv);
+  L.y1 = take(tb * (size_t)L.ldv);
+  L.val32 = take(fp32 ? sizeof(float) * (size_t)std::max(nnz, 1) : 0);
+  L.H = take(sizeof(double) * (M_CAP + 1) * M_CAP);
+  L.ex = take(sizeof(double) * 8 * (size_t)NMAX_EXPM * NMAX_EXPM);
+  L.st = take(sizeof(State));
+  L.stats = take(sizeof(Stats));
+  L.ctl = take(sizeof(TeamCtl));
+  L.part = take(sizeof(double) * (size_t)KMAX * (size_t)gmax);
+  L.res = take(sizeof(double) * KMAX);
+  L.total = off;
+  return L;
+}
+
+thread_local hipStream_t t_last_stream = nullptr;
+thread_local const Stats* t_last_stats = nullptr;
+thread_local const TeamCtl* t_last_ctl = nullptr;
+thread_local int t_last_host_status = 0;
+
+int fail(int code) {
+  t_last_host_status = code;
+  t_last_stats = nullptr;
+  return code;
+}
+
+bool opts_ok(const phipm_opts* o) {
+  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->m_init >= 1 && o->m_max >= o->m_init &&
+         o->m_max <= PHIPM_M_CAP && (o->symm >= -1 && o->symm <= 1) &&
+         (o->precision == PHIPM_FP64 || o->precision == PHIPM_FP32_BASIS) && o->max_attempts >= 1 &&
+         o->workgroups >= 0 && std::isfinite(o->tau_fixed) && o->tau_fixed >= 0.0;
+}
+
+bool csr_ok(const phipm_csr* A) {
+  return A && A->n > 0 && A->nnz >= 0 && A->row_ptr && (A->nnz == 0 || (A->col_idx && A->val));
+}
+
+int choose_workgroups(const phipm_opts* o, int n, int gmax) {
+  int g = o->workgroups;
+  if (g <= 0) {
+    long long want = ((long long)n + 2047) / 2048;
+    g = (int)std::min<long long>(want, gmax);
+  }
+  if (g > gmax) g = gmax;
+  if (g < 1) g = 1;
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+void phipm_default_opts(phipm_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-7;
+  o->symm = -1;
+  o->m_init = 10;
+  o->m_max = 100;
+  o->precision = PHIPM_FP64;
+  o->adapt_m = 1;
+  o->corrector = 1;
+  o->tau_fixed = 0.0;
+  o->max_attempts = 1000000;
+  o->workgroups = 0;
+  o->validate = 1;
+}
+
+int phipm_workspace_bytes(const phipm_csr* A, int p, const phipm_opts* o, size_t* bytes) {
+  if (!csr_ok(A) || p < 0 || p > PHIPM_P_MAX || !opts_ok(o) || !bytes) return PHIPM_EINVAL;
+  const DeviceInfo* d = device_info();
+  if (!d) return PHIPM_EHIP;
+  const bool fp32 = o->precision == PHIPM_FP32_BASIS;
+  const int gmax = fp32 ? d->coresident32 : d->coresident64;
+  const int m_cap = std::min(o->m_max, A->n);
+  *bytes = layout(A->n, A->nnz, p, m_cap, fp32, gmax).total;
+  return PHIPM_OK;
+}
+
+int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts* o, double* u,
+          void* workspace, size_t ws_bytes, phipm_stats* stats, phipm_stream_t stream_) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (!csr_ok(A) || p < 0 || p > PHIPM_P_MAX || !opts_ok(o) || !b || !u || !workspace)
+    return fail(PHIPM_EINVAL);
+  if (!std::isfinite(t)) return fail(PHIPM_ENONFINITE);
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(PHIPM_EINVAL);
+  const DeviceInfo* d = device_info();
+  if (!d) return fail(PHIPM_EHIP);
+  const bool fp32 = o->precision == PHIPM_FP32_BASIS;
+  const int gmax = fp32 ? d->coresident32 : d->coresident64;
+  const int m_cap = std::min(o->m_max, A->n);
+  const Layout L = layout(A->n, A->nnz, p, m_cap, fp32, gmax);
+  if (ws_bytes < L.total) return fail(PHIPM_ENOMEM);
+  // u must not overlap b or the workspace
+  auto overlap = [](const void* a, size_t na, const void* c, size_t nc) {
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(c);
+    return x < y + nc && y < x + na;
+  };
+  const size_t ub = sizeof(double) * (size_t)A->n;
+  if (overlap(u, ub, b, ub * (size_t)(p + 1)) || overlap(u, ub, workspace, ws_bytes))
+    return fail(PHIPM_EINVAL);
+
+  char* ws = static_cast<char*>(workspace);
+  Problem P{};
+  P.n = A->n;
+  P.nnz = A->nnz;
+  P.p = p;
+  P.rp = A->row_ptr;
+  P.ci = A->col_idx;
+  P.val = A->val;
+  P.val32 = reinterpret_cast<float*>(ws + L.val32);
+  P.b = b;
+  P.ldb = A->n;
+  P.u = u;
+  P.t = t;
+  P.tol = o->tol;
+  P.tau_fixed = o->tau_fixed;
+  P.max_attempts = o->max_attempts;
+  P.symm = o->symm;
+  P.m_init = o->m_init;
+  P.m_max = o->m_max;
+  P.adapt_m = o->adapt_m;
+  P.corrector = o->corrector;
+  P.validate = o->validate;
+
+  TeamCtl* ctl = reinterpret_cast<TeamCtl*>(ws + L.ctl);
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  double* res = reinterpret_cast<double*>(ws + L.res);
+  Stats* dstats = reinterpret_cast<Stats*>(ws + L.stats);
+  unsigned long long spin = d->spin_ticks;
+  const int G = choose_workgroups(o, A->n, gmax);
+
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, stream, ctl, 1);
+  if (hipGetLastError() != hipSuccess) return fail(PHIPM_EHIP);
+  hipError_t e;
+  if (fp32) {
+    Work<float> w{reinterpret_cast<double*>(ws + L.W), L.ldw, reinterpret_cast<float*>(ws + L.V),
+                  L.ldv, reinterpret_cast<float*>(ws + L.y0), reinterpret_cast<float*>(ws + L.y1),
+                  reinterpret_cast<double*>(ws + L.H), reinterpret_cast<double*>(ws + L.ex),
+                  reinterpret_cast<State*>(ws + L.st), dstats};
+    void* args[] = {&P, &w, &ctl, &part, &res, &spin};
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_solve<float>), dim3(G),
+                                   dim3(BLOCK), args, 0, stream);
+  } else {
+    Work<double> w{reinterpret_cast<double*>(ws + L.W), L.ldw, reinterpret_cast<double*>(ws + L.V),
+                   L.ldv, reinterpret_cast<double*>(ws + L.y0), reinterpret_cast<double*>(ws + L.y1),
+                   reinterpret_cast<double*>(ws + L.H), reinterpret_cast<double*>(ws + L.ex),
+                   reinterpret_cast<State*>(ws + L.st), dstats};
+    void* args[] = {&P, &w, &ctl, &part, &res, &spin};
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_solve<double>), dim3(G),
+                                   dim3(BLOCK), args, 0, stream);
+  }
+  if (e != hipSuccess) return fail(PHIPM_EHIP);
+  t_last_stream = stream;
+  t_last_stats = dstats;
+  t_last_ctl = ctl;
+  t_last_host_status = PHIPM_OK;
+  if (stats) {
+    Stats hs;
+    TeamCtl hc;
+    if (hipMemcpyAsync(&hs, dstats, sizeof(Stats), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(&hc, ctl, sizeof(TeamCtl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return fail(PHIPM_EHIP);
+    stats->steps = hs.steps;
+    stats->rejected = hs.rejected;
+    stats->matvecs = hs.matvecs;
+    stats->expms = hs.expms;
+    stats->t_reached = hs.t_reached;
+    stats->tau_last = hs.tau_last;
+    stats->m_last = hs.m_last;
+    stats->status = hc.abort ? PHIPM_EABORT : hs.status;
+    stats->lanczos = hs.lanczos;
+    stats->workgroups = G;
+    return stats->status;
+  }
+  return PHIPM_OK;
+}
+
+int phipm_last_status(void) {
+  if (t_last_host_status != PHIPM_OK || !t_last_stats) return t_last_host_status;
+  Stats hs;
+  TeamCtl hc;
+  if (hipMemcpyAsync(&hs, t_last_stats, sizeof(Stats), hipMemcpyDeviceToHost, t_last_stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(&hc, t_last_ctl, sizeof(TeamCtl), hipMemcpyDeviceToHost, t_last_stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(t_last_stream) != hipSuccess)
+    return PHIPM_EHIP;
+  return hc.abort ? PHIPM_EABORT : hs.status;
+}
+
+int phipm_spmv(const phipm_csr* A, const double* x, double* y, phipm_stream_t stream_) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (!csr_ok(A) || !x || !y) return PHIPM_EINVAL;
+  const DeviceInfo* d = device_info();
+  if (!d) return PHIPM_EHIP;
+  const long long tiles = ((long long)A->n + BLOCK - 1) / BLOCK;
+  const int grid = (int)std::min<long long>(tiles, (long long)d->cus * 8);
+  hipLaunchKernelGGL(k_spmv, dim3(grid), dim3(BLOCK), 0, stream, A->n, A->row_ptr, A->col_idx,
+                     A->val, x, y);
+  return hipGetLastError() == hipSuccess ? PHIPM_OK : PHIPM_EHIP;
+}
+
+int phipm_expm(int N, const double* H, double* E, double* scratch, phipm_stream_t stream_) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (N < 1 || N > NMAX_EXPM || !H || !E || !scratch) return PHIPM_EINVAL;
+  hipLaunchKernelGGL(k_expm, dim3(1), dim3(BLOCK), 0, stream, N, H, E, scratch);
+  return hipGetLastError() == hipSuccess ? PHIPM_OK : PHIPM_EHIP;
+}
+
+int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double* V, double* H,
+                 void* workspace, size_t ws_bytes, int* m_done, phipm_stream_t stream_) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (!csr_ok(A) || !v || !V || !H || !workspace || !m_done || m < 1 || m > PHIPM_M_CAP)
+    return PHIPM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return PHIPM_EINVAL;
+  const DeviceInfo* d = device_info();
+  if (!d) return PHIPM_EHIP;
+  const Layout L = layout(A->n, A->nnz, 0, m, false, d->coresident64);
+  if (ws_bytes < L.total) return PHIPM_ENOMEM;
+  char* ws = static_cast<char*>(workspace);
+  Problem P{};
+  P.n = A->n;
+  P.nnz = A->nnz;
+  P.rp = A->row_ptr;
+  P.ci = A->col_idx;
+  P.val = A->val;
+  Work<double> w{nullptr, 0, V, A->n, reinterpret_cast<double*>(ws + L.y0),
+                 reinterpret_cast<double*>(ws + L.y1), reinterpret_cast<double*>(ws + L.H),
+                 nullptr, reinterpret_cast<State*>(ws + L.st), nullptr};
+  TeamCtl* ctl = reinterpret_cast<TeamCtl*>(ws + L.ctl);
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  double* res = reinterpret_cast<double*>(ws + L.res);
+  int* dm = reinterpret_cast<int*>(ws + L.stats);
+  unsigned long long spin = d->spin_ticks;
+  phipm_opts o;
+  phipm_default_opts(&o);
+  const int G = choose_workgroups(&o, A->n, d->coresident64);
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, stream, ctl, 1);
+  void* args[] = {&P, &w, &v, &m, &lanczos, &H, &dm, &ctl, &part, &res, &spin};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_krylov), dim3(G), dim3(BLOCK),
+                                 args, 0, stream) != hipSuccess)
+    return PHIPM_EHIP;
+  if (hipMemcpyAsync(m_done, dm, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return PHIPM_EHIP;
+  return PHIPM_OK;
+}
+
+const char* phipm_status_string(int s) {
+  switch (s) {
+    case PHIPM_OK: return "ok";
+    case PHIPM_EINVAL: return "invalid argument or malformed CSR matrix";
+    case PHIPM_ENOMEM: return "workspace too small";
+    case PHIPM_EHIP: return "HIP runtime error";
+    case PHIPM_ENONFINITE: return "non-finite value in A, b or t";
+    case PHIPM_EMAXSTEPS: return "attempt limit reached";
+    case PHIPM_EUNSUPPORTED: return "unsupported";
+    case PHIPM_EABORT: return "device wait exceeded its time budget";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

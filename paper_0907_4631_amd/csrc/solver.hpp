@@ -1,0 +1,574 @@
+// The adaptive solver of Niesen & Wright (Algorithm 3 with Algorithm 4) run
+// by a team of workgroups of one persistent grid.
+//
+// Every workgroup owns a contiguous block of rows.  All vector work is
+// row-local except the sparse products, which gather from vectors that the
+// team completed before the last team_sync.  Dot products are reduced with
+// team_sync's fused deterministic reduction.  Scalar decisions (small matrix
+// exponential, error estimate, step-size and dimension control) are made by
+// workgroup 0 and published through the State block in device memory; every
+// workgroup reads them after the next team_sync, so control flow is uniform
+// across the team.
+//
+// Data layout in HBM (all column-major, leading dimensions padded to 64):
+//   u            n          float64   output; also w_0
+//   W            n x p      float64   w_1..w_p of eq. wrecurrence
+//   V            n x (m+1)  T         Krylov basis
+//   y[2]         n          T         unnormalised new basis vector (ping-pong)
+//   val32        nnz        float     CSR values rounded to float (T = float)
+//   H            (M_CAP+1) x M_CAP float64, row-major, only read by workgroup 0
+//   ex           8 (m+p+1)^2 float64, the small exponential's scratch
+#pragma once
+#include "controller.hpp"
+#include "dense.hpp"
+#include "spmv.hpp"
+#include "team.hpp"
+
+namespace pkr {
+
+enum {
+  ST_OK = 0,
+  ST_EINVAL = -1,
+  ST_ENONFINITE = -4,
+  ST_EMAXSTEPS = -5,
+  ST_EABORT = -7,
+};
+
+struct Problem {
+  int n, nnz, p;
+  const int* rp;
+  const int* ci;
+  const double* val;
+  float* val32;             // filled by the setup phase when T = float
+  const double* b;          // n x (p+1), leading dimension ldb
+  long long ldb;
+  double* u;
+  double t;                 // signed end time
+  double tol;
+  double tau_fixed;
+  long long max_attempts;
+  int symm, m_init, m_max, adapt_m, corrector, validate;
+};
+
+struct Stats {              // mirrors phipm_stats
+  long long steps, rejected, matvecs, expms;
+  double t_reached, tau_last;
+  int m_last, status, lanczos, workgroups;
+};
+
+struct State {
+  double t_end, sgn, anorm, bnorm, bd_tol;
+  double t, tau, beta;
+  double eps, omega, knorm;
+  int m, m_cap, lanczos, zero_path;
+  int accept, done, status, m_use;
+  double coef[P_MAX + 1];
+  double yb[M_CAP + 2];     // beta*y (0..m_use-1), corrector coefficient at [m_use]
+  Alg4Mem mem;
+  long long steps, rejected, matvecs, expms, attempts;
+  double tau_last;
+  int m_last, pad;
+};
+
+template <typename T>
+struct Work {
+  double* W;
+  long long ldw;
+  T* V;
+  long long ldv;
+  T* y0;
+  T* y1;
+  double* H;
+  double* ex;
+  State* st;
+  Stats* stats;
+};
+
+struct Shared {
+  union {
+    SpmvSmem<double> sm64;
+    SpmvSmem<float> sm32;
+  };
+  double blk[KMAX];
+  double red[KMAX];
+  double h1[KMAX];
+  double coef[P_MAX + 1];
+  double yb[M_CAP + 2];
+};
+
+// Rows owned by this workgroup.  When the team size is a multiple of 8 the
+// blocks are dealt so that the workgroups of one XCD (hardware block ids
+// congruent mod 8) hold neighbouring rows: the stencil gathers then stay in
+// that XCD's L2.
+__device__ __forceinline__ void own_rows(const Team& tm, int n, int& rb, int& re) {
+  int slot = tm.rank;
+  if (tm.size % 8 == 0) slot = (tm.rank % 8) * (tm.size / 8) + tm.rank / 8;
+  long long chunk = ((long long)n + tm.size - 1) / tm.size;
+  chunk = (chunk + 63) / 64 * 64;
+  long long b = (long long)slot * chunk;
+  rb = (int)(b < n ? b : n);
+  long long e = b + chunk;
+  re = (int)(e < n ? e : n);
+}
+
+template <typename T>
+__device__ __forceinline__ SpmvSmem<T>& smem_for(Shared& sh);
+template <>
+__device__ __forceinline__ SpmvSmem<double>& smem_for<double>(Shared& sh) { return sh.sm64; }
+template <>
+__device__ __forceinline__ SpmvSmem<float>& smem_for<float>(Shared& sh) { return sh.sm32; }
+
+// blk[k] = sum over own rows of V[:, i0+k] . y for k < K (block-reduced, float64).
+template <typename T>
+__device__ __forceinline__ void phase_dots(const T* V, long long ldv, int i0, int K, const T* y, int rb, int re,
+                           Shared& sh) {
+  for (int g = 0; g < K; g += 8) {
+    double acc[8];
+    T a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = T(0);
+    const int kk = K - g < 8 ? K - g : 8;
+    for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
+      const T yr = y[r];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < kk) a[q] += V[(long long)(i0 + g + q) * ldv + r] * yr;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = (double)a[q];
+    block_reduce<8>(acc, RED_SUM, sh.blk + g);
+  }
+}
+
+// y -= V[:, i0..i0+K) h over own rows.
+template <typename T>
+__device__ __forceinline__ void phase_project(const T* V, long long ldv, int i0, int K, const double* h, T* y,
+                              int rb, int re) {
+  for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
+    T yr = y[r];
+    for (int k = 0; k < K; ++k) yr -= T(h[k]) * V[(long long)(i0 + k) * ldv + r];
+    y[r] = yr;
+  }
+}
+
+// One step j of the Krylov process (Arnoldi with CGS2, or Lanczos with CGS2
+// against the two previous vectors).  src/scale define v_j = T(src*scale):
+// v_j is written to V[:, j] for own rows and gathered for the product.
+// Returns h_{j+1,j}, or a negative value if the team was aborted.
+template <typename T, typename S>
+__device__ __forceinline__ double krylov_step(const Team& tm, const Problem& P, const Work<T>& w, const T* valT,
+                              double sgn, bool lanczos, int j, const S* src, S scale, int rb,
+                              int re, Shared& sh) {
+  T* y = (j & 1) ? w.y1 : w.y0;
+  T* vj = w.V + (long long)j * w.ldv;
+  auto vload = [&](int c) -> T { return T(src[c] * scale); };
+  // P1: y = A v_j
+  for (int r0 = rb; r0 < re; r0 += BLOCK) {
+    const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
+    T acc = spmv_tile<T, T>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), vload);
+    const int r = r0 + threadIdx.x;
+    if (r < r1) {
+      y[r] = T(sgn) * acc;
+      vj[r] = vload(r);
+    }
+  }
+  const int i0 = lanczos ? (j > 0 ? j - 1 : 0) : 0;
+  const int K = j - i0 + 1;
+  phase_dots<T>(w.V, w.ldv, i0, K, y, rb, re, sh);
+  if (!team_sync(tm, sh.blk, K, RED_SUM, sh.red)) return -1.0;
+  // P2: first projection, then the second pass of dot products
+  for (int k = threadIdx.x; k < K; k += BLOCK) sh.h1[k] = sh.red[k];
+  phase_project<T>(w.V, w.ldv, i0, K, sh.red, y, rb, re);
+  phase_dots<T>(w.V, w.ldv, i0, K, y, rb, re, sh);
+  if (!team_sync(tm, sh.blk, K, RED_SUM, sh.red)) return -1.0;
+  // P3: second projection and the norm
+  phase_project<T>(w.V, w.ldv, i0, K, sh.red, y, rb, re);
+  {
+    double acc[1];
+    T a = T(0);
+    for (int r = rb + threadIdx.x; r < re; r += BLOCK) a += y[r] * y[r];
+    acc[0] = (double)a;
+    if (tm.rank == 0) {
+      // workgroup 0 records column j of H (it alone reads H)
+      for (int i = threadIdx.x; i <= M_CAP; i += BLOCK) {
+        double hv = 0.0;
+        if (i >= i0 && i <= j) hv = sh.h1[i - i0] + sh.red[i - i0];
+        w.H[(long long)i * M_CAP + j] = hv;
+      }
+    }
+    block_reduce<1>(acc, RED_SUM, sh.blk);
+  }
+  if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return -1.0;
+  const double hn = sqrt(sh.red[0]);
+  if (tm.rank == 0 && threadIdx.x == 0) {
+    w.H[(long long)(j + 1) * M_CAP + j] = hn;
+    w.st->matvecs += 1;
+  }
+  return hn;
+}
+
+// Workgroup 0: exponential of the augmented matrix, error estimate and the
+// decisions of Algorithms 3 and 4 for one attempt.
+template <typename T>
+__device__ __forceinline__ void decide(const Problem& P, const Work<T>& w, int have, bool broke, Shared& sh) {
+  State* st = w.st;
+  __shared__ double s_c, s_norm;
+  __shared__ int s_sq;
+  const int p = P.p;
+  const double beta = st->beta;
+  const int m = st->m;
+  const int m_use = beta > 0.0 ? (have < m ? have : m) : m;
+  double tau = st->tau;
+  if (beta > 0.0 && broke && !(P.tau_fixed > 0.0)) tau = st->t_end - st->t;  // exact for any tau
+  double eps = 0.0, hnext = 0.0, knorm = 0.0, c = 0.0;
+  if (beta > 0.0) {
+    hnext = broke ? 0.0 : w.H[(long long)m_use * M_CAP + (m_use - 1)];
+    const int N = m_use + p + 1;
+    double* K = w.ex;
+    for (int e = threadIdx.x; e < N * N; e += BLOCK) {
+      const int i = e / N, jj = e - i * N;
+      double v = 0.0;
+      if (i < m_use && jj < m_use) v = tau * w.H[(long long)i * M_CAP + jj];
+      else if (i == 0 && jj == m_use) v = tau;
+      else if (i >= m_use && i < m_use + p && jj == i + 1) v = tau;
+      K[e] = v;
+    }
+    __syncthreads();
+    const double* E = wg_expm(N, w.ex, &s_norm, &s_sq);
+    const int col = p == 0 ? 0 : m_use + p - 1;
+    for (int k = threadIdx.x; k < m_use; k += BLOCK) st->yb[k] = beta * E[(long long)k * N + col];
+    if (threadIdx.x == 0) s_c = E[(long long)(m_use - 1) * N + m_use + p];
+    __syncthreads();
+    c = s_c;
+    knorm = s_norm;
+    eps = beta * fabs(hnext) * fabs(c);
+  }
+  if (threadIdx.x == 0) {
+    if (beta > 0.0) st->expms += 1;
+    st->attempts += 1;
+    const double t = st->t, t_end = st->t_end;
+    const double omega = t_end * eps / (tau * P.tol);
+    int accept;
+    double tau_next = tau;
+    int m_next = m_use;
+    Alg4Mem& mem = st->mem;
+    if (P.tau_fixed > 0.0) {
+      accept = 1;
+    } else if (!isfinite(omega)) {
+      accept = 0;
+      tau_next = tau / 5.0;
+      mem.rejected = 0;
+    } else {
+      double tau_new, m_new;
+      ctrl_alg4(mem, tau, m_use, eps, omega, &tau_new, &m_new);
+      const double M = ctrl_M(knorm);
+      const double rem = t_end - t;
+      const double m_cost = m_new < 1.0 ? 1.0 : m_new;
+      const bool lz = st->lanczos != 0;
+      const double c_tau = ctrl_C(rem, tau_new, ctrl_C1(lz, m_use, p, P.nnz, P.n, M));
+      const double c_m = ctrl_C(rem, tau, ctrl_C1(lz, m_cost, p, P.nnz, P.n, M));
+      accept = omega <= CTRL_DELTA;
+      int m_cand = m_use;
+      if (P.adapt_m && !broke) {
+        double mm = m_new;
+        const double lo = floor(0.75 * m_use), hi = ceil(4.0 * m_use / 3.0);
+        if (mm < lo) mm = lo;
+        if (mm < 1.0) mm = 1.0;
+        if (mm > hi) mm = hi;
+        if (mm > st->m_cap) mm = st->m_cap;
+        m_cand = (int)mm;
+      }
+      const bool tau_branch =
+          c_tau < c_m || !P.adapt_m || broke || (!accept && m_cand <= m_use);
+      if (tau_branch) {
+        double tn = tau_new;
+        if (tn < tau / 5.0) tn = tau / 5.0;
+        if (tn > 2.0 * tau) tn = 2.0 * tau;
+        if (tn > rem) tn = rem;
+        tau_next = tn;
+      } else {
+        m_next = m_cand;
+      }
+      mem.branch = tau_branch ? 1 : 2;
+      mem.eps = eps;
+      mem.tau = tau;
+      mem.m = m_use;
+      mem.rejected = !accept;
+    }
+    st->eps = eps;
+    st->omega = omega;
+    st->knorm = knorm;
+    st->accept = accept;
+    st->m_use = m_use;
+    if (accept) {
+      double f = 1.0;
+      for (int j = 0; j < p; ++j) {
+        st->coef[j] = f;
+        f *= tau / (double)(j + 1);
+      }
+      st->yb[m_use] = (beta > 0.0 && P.corrector && hnext != 0.0) ? beta * hnext * c : 0.0;
+      double tn = t + tau;
+      if (t_end - tn <= 4.0 * 2.220446049250313e-16 * t_end) tn = t_end;
+      st->t = tn;
+      st->steps += 1;
+      st->tau_last = tau;
+      st->m_last = m_use;
+      st->mem = Alg4Mem{};
+      st->done = tn >= t_end;
+      st->m = m_next;
+      st->tau = tau_next < t_end - tn ? tau_next : t_end - tn;
+    } else {
+      st->rejected += 1;
+      st->tau = tau_next;
+      st->m = m_next;
+    }
+    if (!st->done && st->attempts >= P.max_attempts) {
+      st->status = ST_EMAXSTEPS;
+      st->done = 1;
+      st->accept = 0;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Work<T>& w, Shared& sh) {
+  State* st = w.st;
+  const int tid = threadIdx.x;
+  const int n = P.n, p = P.p;
+  int rb, re;
+  own_rows(tm, n, rb, re);
+  const bool fp32 = sizeof(T) == 4;
+
+  // ---------------------------------------------------------------- setup
+  {
+    // structure / finiteness / symmetry flags and the row sums of |A|
+    double f[4] = {0.0, 0.0, 0.0, 0.0};  // bad, nonfinite, asym, max row sum
+    const bool check_sym = P.symm < 0;
+    for (int r = rb + tid; r < re; r += BLOCK) {
+      const int k0 = P.rp[r], k1 = P.rp[r + 1];
+      if (P.validate) {
+        if (k0 < 0 || k1 < k0 || k1 > P.nnz) { f[0] = 1.0; continue; }
+        if (r == 0 && k0 != 0) f[0] = 1.0;
+        if (r == n - 1 && k1 != P.nnz) f[0] = 1.0;
+      }
+      double s = 0.0;
+      int prev = -1;
+      for (int k = k0; k < k1; ++k) {
+        const int c = P.ci[k];
+        const double a = P.val[k];
+        if (P.validate) {
+          if (c < 0 || c >= n || c <= prev) { f[0] = 1.0; break; }
+          prev = c;
+        }
+        if (!isfinite(a)) f[1] = 1.0;
+        s += fabs(a);
+        if (fp32) P.val32[k] = (float)a;
+        if (check_sym) {
+          const int q0 = P.rp[c], q1 = P.rp[c + 1];
+          bool found = false;
+          if (q0 >= 0 && q1 <= P.nnz && q0 <= q1) {
+            int lo = q0, hi = q1 - 1;
+            while (lo <= hi) {
+              const int mid = (lo + hi) >> 1;
+              const int cm = P.ci[mid];
+              if (cm == r) { found = (P.val[mid] == a); break; }
+              if (cm < r) lo = mid + 1; else hi = mid - 1;
+            }
+          }
+          if (!found) f[2] = 1.0;
+        }
+      }
+      f[3] = nanmax(f[3], s);
+    }
+    block_reduce<4>(f, RED_MAX, sh.blk);
+    // max |b_k| for every k (one block reduction per column)
+    for (int k = 0; k <= p; ++k) {
+      double bm[1] = {0.0};
+      const double* bk = P.b + (long long)k * P.ldb;
+      for (int r = rb + tid; r < re; r += BLOCK) bm[0] = nanmax(bm[0], fabs(bk[r]));
+      block_reduce<1>(bm, RED_MAX, sh.blk + 4 + k);
+    }
+    if (!team_sync(tm, sh.blk, 5 + p, RED_MAX, sh.red)) return;
+    if (tm.rank == 0 && tid == 0) {
+      const double* o = sh.red;
+      st->status = ST_OK;
+      bool nonfinite = o[1] != 0.0 || !isfinite(o[3]) || !isfinite(P.t);
+      for (int k = 0; k <= p; ++k) nonfinite = nonfinite || !isfinite(o[4 + k]);
+      if (o[0] != 0.0) st->status = ST_EINVAL;
+      else if (nonfinite) st->status = ST_ENONFINITE;
+      st->sgn = P.t < 0.0 ? -1.0 : 1.0;
+      st->t_end = fabs(P.t);
+      st->anorm = o[3];
+      double bn = o[4];
+      for (int k = 1; k <= p && bn == 0.0; ++k) bn = o[4 + k];
+      st->bnorm = bn;
+      st->lanczos = P.symm < 0 ? (o[2] == 0.0) : (P.symm != 0);
+      st->zero_path = (st->anorm == 0.0 || bn == 0.0 || st->t_end == 0.0);
+      st->m_cap = P.m_max < n ? P.m_max : n;
+      double tau;
+      if (P.tau_fixed > 0.0) tau = P.tau_fixed;
+      else tau = ctrl_tau0(P.tol, st->anorm, bn, 0.5 * (double)(P.m_init + P.m_max));
+      if (!(tau > 0.0) || !isfinite(tau)) tau = st->t_end;
+      if (tau > st->t_end) tau = st->t_end;
+      st->tau = tau;
+      st->m = P.m_init < st->m_cap ? P.m_init : st->m_cap;
+      st->t = 0.0;
+      st->bd_tol = ldexp(st->anorm, -40);
+      st->done = (st->status != ST_OK);
+      st->steps = st->rejected = st->matvecs = st->expms = st->attempts = 0;
+      st->tau_last = 0.0;
+      st->m_last = 0;
+      st->mem = Alg4Mem{};
+    }
+    if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+  }
+  const double sgn = st->sgn;
+  const double t_end = st->t_end;
+  if (st->status != ST_OK) goto finish;
+
+  if (st->zero_path) {
+    // A = 0, b = 0 or t = 0: u = sum_k t^k/k! b_k (phi_k(0) = 1/k!)
+    double cf[P_MAX + 1];
+    double f = 1.0;
+    for (int k = 0; k <= p; ++k) { cf[k] = f; f *= sgn * t_end / (double)(k + 1); }
+    for (int r = rb + tid; r < re; r += BLOCK) {
+      double s = 0.0;
+      for (int k = 0; k <= p; ++k) s += cf[k] * P.b[(long long)k * P.ldb + r];
+      P.u[r] = s;
+    }
+    if (tm.rank == 0 && tid == 0) st->t = t_end;
+    goto finish;
+  }
+
+  for (int r = rb + tid; r < re; r += BLOCK) P.u[r] = P.b[r];
+  if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+
+  {
+    const T* valT;
+    if constexpr (sizeof(T) == 4) valT = P.val32; else valT = P.val;
+    const bool lanczos = st->lanczos != 0;
+    while (!st->done) {
+      const double t = st->t;
+      // ---- eq. wrecurrence: w_j = A w_{j-1} + sum_l t^l/l! b_{j+l} (A, b scaled by sgn)
+      for (int j = 1; j <= p; ++j) {
+        const double* wprev = j == 1 ? P.u : w.W + (long long)(j - 2) * w.ldw;
+        double* wj = w.W + (long long)(j - 1) * w.ldw;
+        double cf[P_MAX + 1];
+        {
+          double f = 1.0;  // t^l / l!
+          for (int l = 0; l <= p - j; ++l) {
+            const double sg = ((j + l) & 1) ? sgn : 1.0;
+            cf[l] = sg * f;
+            f *= t / (double)(l + 1);
+          }
+        }
+        double nrm = 0.0;
+        auto ld = [&](int c) -> double { return wprev[c]; };
+        for (int r0 = rb; r0 < re; r0 += BLOCK) {
+          const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
+          double acc = spmv_tile<double, double>(P.rp, P.ci, P.val, r0, r1, sh.sm64, ld);
+          const int r = r0 + tid;
+          if (r < r1) {
+            double s = sgn * acc;
+            for (int l = 0; l <= p - j; ++l) s += cf[l] * P.b[(long long)(j + l) * P.ldb + r];
+            wj[r] = s;
+            nrm += s * s;
+          }
+        }
+        if (j == p) {
+          double a1[1] = {nrm};
+          block_reduce<1>(a1, RED_SUM, sh.blk);
+          if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+        } else {
+          if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+        }
+      }
+      if (p == 0) {
+        double a = 0.0;
+        for (int r = rb + tid; r < re; r += BLOCK) a += P.u[r] * P.u[r];
+        double a1[1] = {a};
+        block_reduce<1>(a1, RED_SUM, sh.blk);
+        if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+      }
+      const double beta = sqrt(sh.red[0]);
+      if (tm.rank == 0 && tid == 0) {
+        st->beta = beta;
+        st->matvecs += p;
+        if (!isfinite(beta)) { st->status = ST_ENONFINITE; }
+      }
+      if (!isfinite(beta)) goto finish;
+      const double* wp = p == 0 ? P.u : w.W + (long long)(p - 1) * w.ldw;
+
+      // ---- attempts of this step (Algorithm 3 inner loop)
+      int have = 0;
+      bool broke = false;
+      double hprev = beta;
+      for (;;) {
+        const int m = st->m;
+        if (beta > 0.0) {
+          while (!broke && have < m) {
+            double h;
+            if (have == 0)
+              h = krylov_step<T, double>(tm, P, w, valT, sgn, lanczos, 0, wp, 1.0 / beta, rb, re, sh);
+            else
+              h = krylov_step<T, T>(tm, P, w, valT, sgn, lanczos, have,
+                                    (have - 1) & 1 ? w.y1 : w.y0, T(1.0 / hprev), rb, re, sh);
+            if (h < 0.0) return;  // aborted
+            ++have;
+            hprev = h;
+            if (h <= st->bd_tol || have == n) broke = true;
+          }
+          if (!broke) {
+            // v_have for the corrector (row-local)
+            const T* ys = (have - 1) & 1 ? w.y1 : w.y0;
+            const T sc = T(1.0 / hprev);
+            T* vh = w.V + (long long)have * w.ldv;
+            for (int r = rb + tid; r < re; r += BLOCK) vh[r] = T(ys[r] * sc);
+          }
+        }
+        if (tm.rank == 0) decide<T>(P, w, have, broke, sh);
+        if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+        if (!st->accept) {
+          if (st->done) goto finish;  // attempt limit
+          continue;
+        }
+        // ---- eq. step with the corrected projection eq. phipapprox2
+        const int mu = st->m_use;
+        for (int k = tid; k < p; k += BLOCK) sh.coef[k] = st->coef[k];
+        for (int k = tid; k <= mu; k += BLOCK) sh.yb[k] = st->yb[k];
+        __syncthreads();
+        const bool use_v = beta > 0.0;
+        const bool use_corr = use_v && sh.yb[mu] != 0.0;
+        for (int r = rb + tid; r < re; r += BLOCK) {
+          double s = p > 0 ? sh.coef[0] * P.u[r] : 0.0;
+          for (int j = 1; j < p; ++j) s += sh.coef[j] * w.W[(long long)(j - 1) * w.ldw + r];
+          if (use_v) {
+            for (int k = 0; k < mu; ++k) s += sh.yb[k] * (double)w.V[(long long)k * w.ldv + r];
+            if (use_corr) s += sh.yb[mu] * (double)w.V[(long long)mu * w.ldv + r];
+          }
+          P.u[r] = s;
+        }
+        if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+        break;
+      }
+    }
+  }
+
+finish:
+  if (tm.rank == 0 && tid == 0) {
+    Stats* o = w.stats;
+    o->steps = st->steps;
+    o->rejected = st->rejected;
+    o->matvecs = st->matvecs;
+    o->expms = st->expms;
+    o->t_reached = sgn * st->t;
+    o->tau_last = st->tau_last;
+    o->m_last = st->m_last;
+    o->status = st->status;
+    o->lanczos = st->lanczos;
+    o->workgroups = tm.size;
+  }
+}
+
+}  // namespace pkr

@@ -1,0 +1,285 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Kernel level: CSR product, small exponential, Krylov process.  Solver level:
+fixed (tau, m) stepping (same arithmetic path, tight tolerance), adaptive
+solves (relative 2-norm error <= 10 tol against the oracle), brute force on
+tiny inputs, and the degenerate and error cases of the method.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0907_4631_amd as pk
+    pk.lib()
+    oracle.build(force=False)
+    return pk
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def gpu_solve(pk, t, A, b, **kw):
+    kw.setdefault("max_attempts", 200000)
+    Ad = pk.DeviceCSR(A)
+    bd = dev(np.asarray(b).T)
+    u, st = pk.solve(t, Ad, bd, **kw)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), st
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def ragged_matrix(n, seed):
+    """Rows of very different lengths: empty rows, short rows and rows longer
+    than one LDS tile can stage."""
+    g = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(n):
+        r = g.random()
+        if r < 0.1:
+            k = 0
+        elif r < 0.97:
+            k = int(g.integers(1, 9))
+        else:
+            k = int(g.integers(200, min(n, 6000)))
+        c = np.unique(np.concatenate([[i], g.choice(n, size=k, replace=False)])) if k else []
+        rows += [i] * len(c)
+        cols += list(c)
+    vals = g.standard_normal(len(rows))
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A.sort_indices()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int32)
+    return A
+
+
+# ------------------------------------------------------------ kernel level
+
+@pytest.mark.parametrize("case", ["laplace2d-30", "convdiff-512", "ragged-20000", "laplace3d-64"])
+def test_spmv_matches_oracle(pk, case):
+    say("spmv case", case)
+    A = {"laplace2d-30": lambda: W.laplace2d(30),
+         "convdiff-512": lambda: W.convdiff2d(512, 50.0, 50.0),
+         "ragged-20000": lambda: ragged_matrix(20000, 5),
+         "laplace3d-64": lambda: W.laplace3d(64)}[case]()
+    x = np.random.default_rng(1).standard_normal(A.shape[0])
+    y = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+    pk.spmv(pk.DeviceCSR(A), dev(x), y)
+    torch.cuda.synchronize()
+    ref = oracle.spmv(A, x)
+    scale = abs(A) @ np.abs(x)
+    assert np.all(np.abs(y.cpu().numpy() - ref) <= 1e-14 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("N,scale", [(1, 3.0), (2, 0.5), (5, 40.0), (17, 1.0), (44, 12.0),
+                                     (70, 200.0), (137, 3.0)])
+def test_expm_matches_oracle(pk, N, scale):
+    say("expm case", N, scale)
+    g = np.random.default_rng(N)
+    H = g.standard_normal((N, N)) * scale / math.sqrt(N)
+    E = pk.expm(dev(H)).cpu().numpy()
+    R = oracle.expm(H)
+    assert np.linalg.norm(E - R) <= 1e-13 * N * max(1.0, np.linalg.norm(R))
+
+
+@pytest.mark.parametrize("lanczos", [0, 1])
+def test_krylov_matches_oracle(pk, lanczos):
+    say("krylov case lanczos", lanczos)
+    A = W.laplace2d(40) if lanczos else W.convdiff2d(40, 20.0, 10.0)
+    n = A.shape[0]
+    v = np.random.default_rng(3).standard_normal(n)
+    m = 30
+    V, H, done = pk.krylov(pk.DeviceCSR(A), dev(v), m, lanczos)
+    torch.cuda.synchronize()
+    V, H = V.cpu().numpy(), H.cpu().numpy()
+    Vr, Hr, _, mm = oracle.krylov(A, v, m, lanczos=bool(lanczos), reorth=1)
+    assert done == mm == m
+    hs = np.abs(Hr).max()
+    assert np.abs(H - Hr).max() <= 1e-10 * hs
+    assert np.abs(V - Vr).max() <= 1e-9
+    G = V.T @ V
+    if not lanczos:
+        assert np.abs(G - np.eye(m + 1)).max() < 1e-13
+    AV = A @ V[:, :m]
+    assert np.linalg.norm(AV - V @ H) <= 1e-12 * sp.linalg.norm(A) * math.sqrt(m)
+
+
+# ------------------------------------------------------------ solver level
+
+FIXED = [
+    # name, matrix builder, p, t, tau, m
+    ("lap2d-30 p1", lambda: W.laplace2d(30), 1, 1e-3, 1e-4, 12),
+    ("convdiff-64 p3", lambda: W.convdiff2d(64, 30.0, 30.0), 3, 1e-3, 2.5e-4, 20),
+    ("ragged-3000 p0", lambda: ragged_matrix(3000, 7) * 0.05, 0, 0.3, 0.1, 15),
+]
+
+
+@pytest.mark.parametrize("name,build,p,t,tau,m", FIXED)
+def test_fixed_tau_m_stepping_matches_oracle(pk, name, build, p, t, tau, m):
+    """Same path on both sides: fixed substeps, fixed m, every step accepted."""
+    say("fixed-step case", name)
+    A = build()
+    n = A.shape[0]
+    b = np.random.default_rng(11).standard_normal((n, p + 1))
+    kw = dict(tau_fixed=tau, m_init=m, m_max=m, adapt_m=0)
+    u, st = gpu_solve(pk, t, A, b, **kw)
+    ref, ost = oracle.phipm(t, A, b, **kw)
+    assert st["status"] == 0
+    assert st["steps"] == ost["steps"] and st["matvecs"] == ost["matvecs"]
+    assert rel(u, ref) <= 1e-11, rel(u, ref)
+
+
+ADAPTIVE = [
+    # name, builder, p, t, tol
+    ("config1 lap2d-30 p1", None, 1, 1e-3, 1e-7),
+    ("lap2d-50 p0", lambda: W.laplace2d(50), 0, 2e-3, 1e-8),
+    ("convdiff-48 p2", lambda: W.convdiff2d(48, 40.0, 20.0), 2, 5e-3, 1e-8),
+    ("convdiff-32 p4 negative t", lambda: W.convdiff2d(32, 10.0, 0.0), 4, -2e-4, 1e-9),
+    ("reaction-64 p2", lambda: W.reaction2d(64, 5999), 2, 1e-3, 1e-6),
+    ("ragged-2000 p1", lambda: ragged_matrix(2000, 3) * 0.1, 1, 1.0, 1e-8),
+]
+
+
+@pytest.mark.parametrize("name,build,p,t,tol", ADAPTIVE)
+def test_adaptive_matches_oracle(pk, name, build, p, t, tol):
+    say("adaptive case", name)
+    if build is None:
+        pb = W.config1()
+        A, b = pb.A, pb.b
+    else:
+        A = build()
+        b = np.random.default_rng(5).standard_normal((A.shape[0], p + 1))
+    u, st = gpu_solve(pk, t, A, b, tol=tol)
+    ref, ost = oracle.phipm(t, A, b, tol=tol)
+    say("  gpu", st, "\n  oracle", ost, "\n  rel", rel(u, ref))
+    assert st["status"] == 0
+    assert rel(u, ref) <= 10 * tol
+    assert st["lanczos"] == int(oracle.is_symmetric(A))
+
+
+def brute_force(A, b, t):
+    import scipy.linalg as sla
+    A = A.toarray()
+    n, p1 = b.shape
+    p = p1 - 1
+    M = np.zeros((n + p, n + p))
+    M[:n, :n] = A
+    for i in range(p):
+        M[:n, n + i] = b[:, p - i]
+        if i + 1 < p:
+            M[n + i, n + i + 1] = 1.0
+    x0 = np.zeros(n + p)
+    x0[:n] = b[:, 0]
+    if p > 0:
+        x0[n + p - 1] = 1.0
+    return (sla.expm(t * M) @ x0)[:n]
+
+
+@pytest.mark.parametrize("p", [0, 2, 4])
+def test_tiny_vs_bruteforce(pk, p):
+    say("tiny brute-force case p", p)
+    A = W.random_sparse(60, 0.1, seed=p, shift=-3.0) * 6.0
+    b = np.random.default_rng(p).standard_normal((60, p + 1))
+    tol = 1e-8
+    u, st = gpu_solve(pk, 1.0, A, b, tol=tol)
+    ref = brute_force(A, b, 1.0)
+    assert st["status"] == 0
+    assert np.linalg.norm(u - ref) <= 10 * tol
+
+
+def test_eigenvector_decay_is_exact(pk):
+    say("eigenvector decay")
+    A = W.laplace2d(30)
+    v, lam = W.sine_mode2d(30, 2, 3)
+    c = np.array([1.0, -0.5, 2.0])
+    b = np.outer(v, c)
+    t = 1e-3
+    u, st = gpu_solve(pk, t, A, b, tol=1e-10)
+    ref = sum(t ** k * oracle.phi(k, t * lam) * c[k] for k in range(3)) * v
+    assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert st["steps"] == 1 and st["rejected"] == 0
+
+
+def test_degenerate_inputs(pk):
+    say("degenerate inputs")
+    A = W.laplace2d(10)
+    n = 100
+    b = np.random.default_rng(0).standard_normal((n, 3))
+    u, st = gpu_solve(pk, 0.0, A, b)                      # t = 0: u = b0
+    assert np.array_equal(u, b[:, 0]) and st["steps"] == 0
+    Z = sp.csr_matrix((n, n))
+    Z.indptr = Z.indptr.astype(np.int32)
+    Z.indices = Z.indices.astype(np.int32)
+    u, st = gpu_solve(pk, 0.7, Z, b)                      # A = 0
+    ref = sum(0.7 ** k / math.factorial(k) * b[:, k] for k in range(3))
+    assert np.allclose(u, ref, rtol=1e-15, atol=1e-15)
+    u, st = gpu_solve(pk, 0.01, A, np.zeros((n, 3)))      # b = 0
+    assert np.all(u == 0.0)
+    one = sp.csr_matrix(np.array([[-2.0]]))               # n = 1
+    one.indptr = one.indptr.astype(np.int32)
+    one.indices = one.indices.astype(np.int32)
+    bb = np.array([[1.5, 0.5]])
+    u, st = gpu_solve(pk, 0.3, one, bb, tol=1e-12)
+    ref = math.exp(-0.6) * 1.5 + 0.3 * oracle.phi(1, -0.6) * 0.5
+    assert abs(u[0] - ref) <= 1e-13
+    # largest p
+    b8 = np.random.default_rng(1).standard_normal((n, 9))
+    u, st = gpu_solve(pk, 2e-3, A, b8, tol=1e-9)
+    ref, _ = oracle.phipm(2e-3, A, b8, tol=1e-9)
+    assert rel(u, ref) <= 1e-8
+
+
+def test_error_reporting(pk):
+    say("error reporting")
+    A = W.laplace2d(8)
+    n = 64
+    b = np.random.default_rng(0).standard_normal((n, 2))
+    bn = b.copy()
+    bn[5, 1] = np.nan
+    with pytest.raises(pk.PhipmError) as e:
+        gpu_solve(pk, 1e-3, A, bn)
+    assert e.value.status == pk.ENONFINITE
+    bad = A.copy()
+    bad.indices = bad.indices.copy()
+    bad.indices[3], bad.indices[4] = bad.indices[4], bad.indices[3]   # unsorted row
+    with pytest.raises(pk.PhipmError) as e:
+        gpu_solve(pk, 1e-3, bad, b)
+    assert e.value.status == pk.EINVAL
+    with pytest.raises(pk.PhipmError) as e:
+        gpu_solve(pk, 1.0, A, b, max_attempts=2, tol=1e-12)
+    assert e.value.status == pk.EMAXSTEPS
+    with pytest.raises(pk.PhipmError) as e:
+        gpu_solve(pk, 1.0, A, b, m_max=pk.M_CAP + 1)
+    assert e.value.status == pk.EINVAL
+
+
+@pytest.mark.parametrize("wg", [1, 3, 8, 64])
+def test_workgroup_count_does_not_change_result(pk, wg):
+    say("workgroups", wg)
+    A = W.convdiff2d(96, 25.0, 5.0)
+    b = np.random.default_rng(2).standard_normal((A.shape[0], 2))
+    u, st = gpu_solve(pk, 2e-3, A, b, tol=1e-9, workgroups=wg)
+    ref, _ = oracle.phipm(2e-3, A, b, tol=1e-9)
+    assert st["workgroups"] == wg
+    assert rel(u, ref) <= 1e-8
