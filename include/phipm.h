@@ -89,6 +89,9 @@ typedef struct {
   int32_t status;    /* PHIPM_OK or an error code */
   int32_t lanczos;   /* 1 if the Lanczos (symmetric) path was used */
   int32_t workgroups;/* workgroups that cooperated on the solve */
+  double anorm;      /* ||A||_inf as used by eq. tau_0 */
+  int32_t setup_flags; /* bit 0: malformed CSR, bit 1: non-finite data, bit 2: A != A^T */
+  int32_t pad_;
 } phipm_stats;
 
 void phipm_default_opts(phipm_opts* opts);

@@ -325,6 +325,9 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
     stats->status = hc.abort ? PHIPM_EABORT : hs.status;
     stats->lanczos = hs.lanczos;
     stats->workgroups = G;
+    stats->anorm = hs.anorm;
+    stats->setup_flags = hs.setup_flags;
+    stats->pad_ = 0;
     return stats->status;
   }
   return PHIPM_OK;

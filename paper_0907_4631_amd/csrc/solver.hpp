@@ -54,11 +54,14 @@ struct Stats {              // mirrors phipm_stats
   long long steps, rejected, matvecs, expms;
   double t_reached, tau_last;
   int m_last, status, lanczos, workgroups;
+  double anorm;
+  int setup_flags, pad;
 };
 
 struct State {
   double t_end, sgn, anorm, bnorm, bd_tol;
   double t, tau, beta;
+  int setup_flags, pad0;
   double eps, omega, knorm;
   int m, m_cap, lanczos, zero_path;
   int accept, done, status, m_use;
@@ -347,36 +350,44 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
     const bool check_sym = P.symm < 0;
     for (int r = rb + tid; r < re; r += BLOCK) {
       const int k0 = P.rp[r], k1 = P.rp[r + 1];
+      bool row_ok = true;
       if (P.validate) {
-        if (k0 < 0 || k1 < k0 || k1 > P.nnz) { f[0] = 1.0; continue; }
+        if (k0 < 0 || k1 < k0 || k1 > P.nnz) { f[0] = 1.0; row_ok = false; }
         if (r == 0 && k0 != 0) f[0] = 1.0;
         if (r == n - 1 && k1 != P.nnz) f[0] = 1.0;
       }
       double s = 0.0;
       int prev = -1;
-      for (int k = k0; k < k1; ++k) {
+      // (loops below avoid `break`: the compiler has dropped flag updates
+      // after early exits from nested divergent loops)
+      for (int k = k0; k < k1 && row_ok; ++k) {
         const int c = P.ci[k];
         const double a = P.val[k];
-        if (P.validate) {
-          if (c < 0 || c >= n || c <= prev) { f[0] = 1.0; break; }
+        if (P.validate && (c < 0 || c >= n || c <= prev)) {
+          f[0] = 1.0;
+          row_ok = false;
+        } else {
           prev = c;
-        }
-        if (!isfinite(a)) f[1] = 1.0;
-        s += fabs(a);
-        if (fp32) P.val32[k] = (float)a;
-        if (check_sym) {
-          const int q0 = P.rp[c], q1 = P.rp[c + 1];
-          bool found = false;
-          if (q0 >= 0 && q1 <= P.nnz && q0 <= q1) {
-            int lo = q0, hi = q1 - 1;
-            while (lo <= hi) {
-              const int mid = (lo + hi) >> 1;
-              const int cm = P.ci[mid];
-              if (cm == r) { found = (P.val[mid] == a); break; }
-              if (cm < r) lo = mid + 1; else hi = mid - 1;
+          if (!isfinite(a)) f[1] = 1.0;
+          s += fabs(a);
+          if (fp32) P.val32[k] = (float)a;
+          if (check_sym) {
+            // binary search of row c for column r
+            const int q0 = P.rp[c], q1 = P.rp[c + 1];
+            int pos = -1;
+            if (q0 >= 0 && q1 <= P.nnz && q0 <= q1) {
+              int lo = q0, hi = q1 - 1;
+              while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int cm = P.ci[mid];
+                if (cm < r) lo = mid + 1;
+                else if (cm > r) hi = mid - 1;
+                else { pos = mid; lo = hi + 1; }
+              }
             }
+            const bool mirrored = pos >= 0 && P.val[pos] == a;
+            f[2] = mirrored ? f[2] : 1.0;
           }
-          if (!found) f[2] = 1.0;
         }
       }
       f[3] = nanmax(f[3], s);
@@ -404,6 +415,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
       for (int k = 1; k <= p && bn == 0.0; ++k) bn = o[4 + k];
       st->bnorm = bn;
       st->lanczos = P.symm < 0 ? (o[2] == 0.0) : (P.symm != 0);
+      st->setup_flags = (o[0] != 0.0 ? 1 : 0) | (o[1] != 0.0 ? 2 : 0) | (o[2] != 0.0 ? 4 : 0);
       st->zero_path = (st->anorm == 0.0 || bn == 0.0 || st->t_end == 0.0);
       st->m_cap = P.m_max < n ? P.m_max : n;
       double tau;
@@ -568,6 +580,8 @@ finish:
     o->status = st->status;
     o->lanczos = st->lanczos;
     o->workgroups = tm.size;
+    o->anorm = st->anorm;
+    o->setup_flags = st->setup_flags;
   }
 }
 

@@ -132,15 +132,16 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
     }
   } else if (tid == 0) {
     const uint64_t t0 = wall_clock64();
-    while (ld_acquire(&tm.ctl->gen) == g) {
+    int ok = 1;
+    while (ok && ld_acquire(&tm.ctl->gen) == g) {
       __builtin_amdgcn_s_sleep(2);
-      if (ld_relaxed(&tm.ctl->abort)) { s_ok = 0; break; }
-      if (wall_clock64() - t0 > tm.spin_ticks) {
+      if (ld_relaxed(&tm.ctl->abort)) ok = 0;
+      else if (wall_clock64() - t0 > tm.spin_ticks) {
         st_relaxed(&tm.ctl->abort, 1u);
-        s_ok = 0;
-        break;
+        ok = 0;
       }
     }
+    s_ok = ok;
   }
   __syncthreads();
   if (!s_ok) return false;

@@ -146,6 +146,7 @@ def test_fixed_tau_m_stepping_matches_oracle(pk, name, build, p, t, tau, m):
     u, st = gpu_solve(pk, t, A, b, **kw)
     ref, ost = oracle.phipm(t, A, b, **kw)
     assert st["status"] == 0
+    assert st["lanczos"] == int(oracle.is_symmetric(A))
     assert st["steps"] == ost["steps"] and st["matvecs"] == ost["matvecs"]
     assert rel(u, ref) <= 1e-11, rel(u, ref)
 
@@ -176,6 +177,8 @@ def test_adaptive_matches_oracle(pk, name, build, p, t, tol):
     assert st["status"] == 0
     assert rel(u, ref) <= 10 * tol
     assert st["lanczos"] == int(oracle.is_symmetric(A))
+    assert (st["setup_flags"] >> 2 & 1) == 1 - st["lanczos"]
+    assert st["anorm"] == pytest.approx(abs(A).sum(axis=1).max(), rel=1e-14)
 
 
 def brute_force(A, b, t):
