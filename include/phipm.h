@@ -92,6 +92,8 @@ typedef struct {
   double anorm;      /* ||A||_inf as used by eq. tau_0 */
   int32_t setup_flags; /* bit 0: malformed CSR, bit 1: non-finite data, bit 2: A != A^T */
   int32_t pad_;
+  double bytes;      /* algorithmic HBM bytes of the streaming phases: every CSR array,
+                        basis column and vector counted once per pass that touches it */
 } phipm_stats;
 
 void phipm_default_opts(phipm_opts* opts);

@@ -75,6 +75,8 @@ def lib():
             build()
         L = C.CDLL(_LIB)
         L.oracle_default_opts.argtypes = [C.POINTER(Opts)]
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = C.c_int
         L.oracle_phi.argtypes = [C.c_int, C.c_double]
         L.oracle_phi.restype = C.c_double
         L.oracle_expm.argtypes = [C.c_int, _dp, _dp]
@@ -186,8 +188,14 @@ def alg4(state: Alg4State, tau, m, eps, omega):
     return tn.value, mn.value, q.value, k.value
 
 
-def phipm(t, A, b, opts: Opts | None = None, trace_cap: int = 0, **kw):
-    """u = sum_k t^k phi_k(tA) b_k; b is n x (p+1).  Returns (u, stats[, trace])."""
+def threads() -> int:
+    return lib().oracle_threads()
+
+
+def phipm(t, A, b, opts: Opts | None = None, trace_cap: int = 0, allow_limit: bool = False,
+          **kw):
+    """u = sum_k t^k phi_k(tA) b_k; b is n x (p+1).  Returns (u, stats[, trace]).
+    allow_limit: return normally when the attempt limit stops the solve."""
     if opts is None:
         opts = default_opts(**kw)
     rp, ci, va = _csr(A)
@@ -204,7 +212,7 @@ def phipm(t, A, b, opts: Opts | None = None, trace_cap: int = 0, **kw):
     rc = lib().oracle_phipm(float(t), n, rp, ci, va, p, bcm, C.byref(opts), u, C.byref(st),
                             C.cast(tr, C.c_void_p) if tr is not None else None, trace_cap,
                             C.byref(tl))
-    if rc != 0:
+    if rc != 0 and not (allow_limit and rc == -5):
         raise RuntimeError(f"oracle_phipm failed with status {rc}")
     if trace_cap > 0:
         recs = [{k: getattr(tr[i], k) for k, _ in TraceRec._fields_} for i in range(tl.value)]

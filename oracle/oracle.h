@@ -69,6 +69,9 @@ enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_EMAXSTEPS = -5, ORACLE_ENONFINI
 
 void   oracle_default_opts(oracle_opts* o);
 
+/* threads the OpenMP loops use */
+int    oracle_threads(void);
+
 /* scalar phi_k(z), k >= 0 */
 double oracle_phi(int k, double z);
 

@@ -15,6 +15,9 @@
 
 #include <float.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -31,6 +34,14 @@ void oracle_default_opts(oracle_opts* o) {
   o->corrector = 1;
   o->tau_fixed = 0.0;
   o->max_attempts = 1000000;
+}
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /* ------------------------------------------------------- scalar phi_k(z) */

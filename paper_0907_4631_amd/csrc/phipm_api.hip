@@ -16,15 +16,15 @@ namespace {
 // ------------------------------------------------------------ kernels
 
 __global__ void k_zero_ctl(TeamCtl* ctl, int count) {
-  for (int i = threadIdx.x; i < count; i += blockDim.x) {
-    ctl[i].count = 0u;
-    ctl[i].gen = 0u;
-    ctl[i].abort = 0u;
-  }
+  unsigned* w = reinterpret_cast<unsigned*>(ctl);
+  const size_t words = (size_t)count * sizeof(TeamCtl) / sizeof(unsigned);
+  for (size_t i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0u;
 }
 
+// At most 128 VGPRs, so that two 512-thread workgroups share a CU (the
+// streaming phases need the extra waves in flight).
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_solve(Problem P, Work<T> w, TeamCtl* ctl,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_solve(Problem P, Work<T> w, TeamCtl* ctl,
                                                  double* partials, double* result,
                                                  unsigned long long spin) {
   __shared__ Shared sh;
@@ -123,8 +123,8 @@ const DeviceInfo* device_info() {
       return nullptr;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, k_solve<float>, BLOCK, 0) != hipSuccess)
       return nullptr;
-    d.coresident64 = std::max(1, b64) * d.cus;
-    d.coresident32 = std::max(1, b32) * d.cus;
+    d.coresident64 = std::min(TEAM_MAX, std::max(1, b64) * d.cus);
+    d.coresident32 = std::min(TEAM_MAX, std::max(1, b32) * d.cus);
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
       khz = 100000;
@@ -159,7 +159,7 @@ Layout layout(int n, int nnz, int p, int m_cap, bool fp32, int gmax) {
   L.st = take(sizeof(State));
   L.stats = take(sizeof(Stats));
   L.ctl = take(sizeof(TeamCtl));
-  L.part = take(sizeof(double) * (size_t)KMAX * (size_t)gmax);
+  L.part = take(sizeof(double) * (size_t)KMAX * ((size_t)gmax + TEAM_NGROUPS));
   L.res = take(sizeof(double) * KMAX);
   L.total = off;
   return L;
@@ -283,7 +283,7 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   unsigned long long spin = d->spin_ticks;
   const int G = choose_workgroups(o, A->n, gmax);
 
-  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, stream, ctl, 1);
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, stream, ctl, 1);
   if (hipGetLastError() != hipSuccess) return fail(PHIPM_EHIP);
   hipError_t e;
   if (fp32) {
@@ -328,6 +328,7 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
     stats->anorm = hs.anorm;
     stats->setup_flags = hs.setup_flags;
     stats->pad_ = 0;
+    stats->bytes = hs.bytes;
     return stats->status;
   }
   return PHIPM_OK;
@@ -393,7 +394,7 @@ int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double
   phipm_opts o;
   phipm_default_opts(&o);
   const int G = choose_workgroups(&o, A->n, d->coresident64);
-  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, stream, ctl, 1);
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, stream, ctl, 1);
   void* args[] = {&P, &w, &v, &m, &lanczos, &H, &dm, &ctl, &part, &res, &spin};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_krylov), dim3(G), dim3(BLOCK),
                                  args, 0, stream) != hipSuccess)

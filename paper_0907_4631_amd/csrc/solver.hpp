@@ -56,11 +56,13 @@ struct Stats {              // mirrors phipm_stats
   int m_last, status, lanczos, workgroups;
   double anorm;
   int setup_flags, pad;
+  double bytes;
 };
 
 struct State {
   double t_end, sgn, anorm, bnorm, bd_tol;
   double t, tau, beta;
+  double bytes;             // algorithmic HBM bytes so far
   int setup_flags, pad0;
   double eps, omega, knorm;
   int m, m_cap, lanczos, zero_path;
@@ -98,6 +100,11 @@ struct Shared {
   double coef[P_MAX + 1];
   double yb[M_CAP + 2];
 };
+
+// Algorithmic HBM bytes of one CSR product y = A x with value/vector width s.
+__device__ __forceinline__ double spmv_bytes(const Problem& P, double s) {
+  return (s + 4.0) * P.nnz + 4.0 * (P.n + 1.0) + 2.0 * s * P.n;
+}
 
 // Rows owned by this workgroup.  When the team size is a multiple of 8 the
 // blocks are dealt so that the workgroups of one XCD (hardware block ids
@@ -206,38 +213,49 @@ __device__ __forceinline__ double krylov_step(const Team& tm, const Problem& P, 
   if (tm.rank == 0 && threadIdx.x == 0) {
     w.H[(long long)(j + 1) * M_CAP + j] = hn;
     w.st->matvecs += 1;
+    // product, v_j store, and the K-column passes of P1 (K+1), P2 (2K+3), P3 (K+3)
+    w.st->bytes += spmv_bytes(P, sizeof(T)) + (4.0 * K + 8.0) * sizeof(T) * (double)P.n;
   }
   return hn;
 }
 
+// Scalars the decision step needs (passed by value so that the out-of-line
+// call does not force the kernel arguments into private memory).
+struct DecideArgs {
+  double tol, tau_fixed, nnz, n;
+  long long max_attempts;
+  int p, adapt_m, corrector, have, broke;
+};
+
 // Workgroup 0: exponential of the augmented matrix, error estimate and the
-// decisions of Algorithms 3 and 4 for one attempt.
-template <typename T>
-__device__ __forceinline__ void decide(const Problem& P, const Work<T>& w, int have, bool broke, Shared& sh) {
-  State* st = w.st;
+// decisions of Algorithms 3 and 4 for one attempt.  Kept out of line: it is
+// cold code with high register pressure.
+__device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, double* ex) {
   __shared__ double s_c, s_norm;
   __shared__ int s_sq;
-  const int p = P.p;
+  const int p = a.p;
+  const int have = a.have;
+  const bool broke = a.broke != 0;
   const double beta = st->beta;
   const int m = st->m;
   const int m_use = beta > 0.0 ? (have < m ? have : m) : m;
   double tau = st->tau;
-  if (beta > 0.0 && broke && !(P.tau_fixed > 0.0)) tau = st->t_end - st->t;  // exact for any tau
+  if (beta > 0.0 && broke && !(a.tau_fixed > 0.0)) tau = st->t_end - st->t;  // exact for any tau
   double eps = 0.0, hnext = 0.0, knorm = 0.0, c = 0.0;
   if (beta > 0.0) {
-    hnext = broke ? 0.0 : w.H[(long long)m_use * M_CAP + (m_use - 1)];
+    hnext = broke ? 0.0 : H[(long long)m_use * M_CAP + (m_use - 1)];
     const int N = m_use + p + 1;
-    double* K = w.ex;
+    double* K = ex;
     for (int e = threadIdx.x; e < N * N; e += BLOCK) {
       const int i = e / N, jj = e - i * N;
       double v = 0.0;
-      if (i < m_use && jj < m_use) v = tau * w.H[(long long)i * M_CAP + jj];
+      if (i < m_use && jj < m_use) v = tau * H[(long long)i * M_CAP + jj];
       else if (i == 0 && jj == m_use) v = tau;
       else if (i >= m_use && i < m_use + p && jj == i + 1) v = tau;
       K[e] = v;
     }
     __syncthreads();
-    const double* E = wg_expm(N, w.ex, &s_norm, &s_sq);
+    const double* E = wg_expm(N, ex, &s_norm, &s_sq);
     const int col = p == 0 ? 0 : m_use + p - 1;
     for (int k = threadIdx.x; k < m_use; k += BLOCK) st->yb[k] = beta * E[(long long)k * N + col];
     if (threadIdx.x == 0) s_c = E[(long long)(m_use - 1) * N + m_use + p];
@@ -250,12 +268,12 @@ __device__ __forceinline__ void decide(const Problem& P, const Work<T>& w, int h
     if (beta > 0.0) st->expms += 1;
     st->attempts += 1;
     const double t = st->t, t_end = st->t_end;
-    const double omega = t_end * eps / (tau * P.tol);
+    const double omega = t_end * eps / (tau * a.tol);
     int accept;
     double tau_next = tau;
     int m_next = m_use;
     Alg4Mem& mem = st->mem;
-    if (P.tau_fixed > 0.0) {
+    if (a.tau_fixed > 0.0) {
       accept = 1;
     } else if (!isfinite(omega)) {
       accept = 0;
@@ -268,11 +286,11 @@ __device__ __forceinline__ void decide(const Problem& P, const Work<T>& w, int h
       const double rem = t_end - t;
       const double m_cost = m_new < 1.0 ? 1.0 : m_new;
       const bool lz = st->lanczos != 0;
-      const double c_tau = ctrl_C(rem, tau_new, ctrl_C1(lz, m_use, p, P.nnz, P.n, M));
-      const double c_m = ctrl_C(rem, tau, ctrl_C1(lz, m_cost, p, P.nnz, P.n, M));
+      const double c_tau = ctrl_C(rem, tau_new, ctrl_C1(lz, m_use, p, a.nnz, a.n, M));
+      const double c_m = ctrl_C(rem, tau, ctrl_C1(lz, m_cost, p, a.nnz, a.n, M));
       accept = omega <= CTRL_DELTA;
       int m_cand = m_use;
-      if (P.adapt_m && !broke) {
+      if (a.adapt_m && !broke) {
         double mm = m_new;
         const double lo = floor(0.75 * m_use), hi = ceil(4.0 * m_use / 3.0);
         if (mm < lo) mm = lo;
@@ -282,7 +300,7 @@ __device__ __forceinline__ void decide(const Problem& P, const Work<T>& w, int h
         m_cand = (int)mm;
       }
       const bool tau_branch =
-          c_tau < c_m || !P.adapt_m || broke || (!accept && m_cand <= m_use);
+          c_tau < c_m || !a.adapt_m || broke || (!accept && m_cand <= m_use);
       if (tau_branch) {
         double tn = tau_new;
         if (tn < tau / 5.0) tn = tau / 5.0;
@@ -309,7 +327,7 @@ __device__ __forceinline__ void decide(const Problem& P, const Work<T>& w, int h
         st->coef[j] = f;
         f *= tau / (double)(j + 1);
       }
-      st->yb[m_use] = (beta > 0.0 && P.corrector && hnext != 0.0) ? beta * hnext * c : 0.0;
+      st->yb[m_use] = (beta > 0.0 && a.corrector && hnext != 0.0) ? beta * hnext * c : 0.0;
       double tn = t + tau;
       if (t_end - tn <= 4.0 * 2.220446049250313e-16 * t_end) tn = t_end;
       st->t = tn;
@@ -325,7 +343,7 @@ __device__ __forceinline__ void decide(const Problem& P, const Work<T>& w, int h
       st->tau = tau_next;
       st->m = m_next;
     }
-    if (!st->done && st->attempts >= P.max_attempts) {
+    if (!st->done && st->attempts >= a.max_attempts) {
       st->status = ST_EMAXSTEPS;
       st->done = 1;
       st->accept = 0;
@@ -432,6 +450,8 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
       st->tau_last = 0.0;
       st->m_last = 0;
       st->mem = Alg4Mem{};
+      st->bytes = (check_sym ? 24.0 : 12.0) * P.nnz + 4.0 * (n + 1.0) + 8.0 * n * (p + 1.0) +
+                  (fp32 ? 4.0 * P.nnz : 0.0);
     }
     if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
   }
@@ -441,12 +461,12 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
 
   if (st->zero_path) {
     // A = 0, b = 0 or t = 0: u = sum_k t^k/k! b_k (phi_k(0) = 1/k!)
-    double cf[P_MAX + 1];
-    double f = 1.0;
-    for (int k = 0; k <= p; ++k) { cf[k] = f; f *= sgn * t_end / (double)(k + 1); }
     for (int r = rb + tid; r < re; r += BLOCK) {
-      double s = 0.0;
-      for (int k = 0; k <= p; ++k) s += cf[k] * P.b[(long long)k * P.ldb + r];
+      double s = 0.0, f = 1.0;
+      for (int k = 0; k <= p; ++k) {
+        s += f * P.b[(long long)k * P.ldb + r];
+        f *= sgn * t_end / (double)(k + 1);
+      }
       P.u[r] = s;
     }
     if (tm.rank == 0 && tid == 0) st->t = t_end;
@@ -454,6 +474,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
   }
 
   for (int r = rb + tid; r < re; r += BLOCK) P.u[r] = P.b[r];
+  if (tm.rank == 0 && tid == 0) st->bytes += 16.0 * n;
   if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
 
   {
@@ -466,15 +487,6 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
       for (int j = 1; j <= p; ++j) {
         const double* wprev = j == 1 ? P.u : w.W + (long long)(j - 2) * w.ldw;
         double* wj = w.W + (long long)(j - 1) * w.ldw;
-        double cf[P_MAX + 1];
-        {
-          double f = 1.0;  // t^l / l!
-          for (int l = 0; l <= p - j; ++l) {
-            const double sg = ((j + l) & 1) ? sgn : 1.0;
-            cf[l] = sg * f;
-            f *= t / (double)(l + 1);
-          }
-        }
         double nrm = 0.0;
         auto ld = [&](int c) -> double { return wprev[c]; };
         for (int r0 = rb; r0 < re; r0 += BLOCK) {
@@ -483,11 +495,16 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
           const int r = r0 + tid;
           if (r < r1) {
             double s = sgn * acc;
-            for (int l = 0; l <= p - j; ++l) s += cf[l] * P.b[(long long)(j + l) * P.ldb + r];
+            double f = 1.0;  // t^l / l!, times the sign of b_{j+l}
+            for (int l = 0; l <= p - j; ++l) {
+              s += (((j + l) & 1) ? sgn * f : f) * P.b[(long long)(j + l) * P.ldb + r];
+              f *= t / (double)(l + 1);
+            }
             wj[r] = s;
             nrm += s * s;
           }
         }
+        if (tm.rank == 0 && tid == 0) st->bytes += spmv_bytes(P, 8.0) + 8.0 * n * (p - j + 1.0);
         if (j == p) {
           double a1[1] = {nrm};
           block_reduce<1>(a1, RED_SUM, sh.blk);
@@ -498,6 +515,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
       }
       if (p == 0) {
         double a = 0.0;
+        if (tm.rank == 0 && tid == 0) st->bytes += 8.0 * n;
         for (int r = rb + tid; r < re; r += BLOCK) a += P.u[r] * P.u[r];
         double a1[1] = {a};
         block_reduce<1>(a1, RED_SUM, sh.blk);
@@ -537,9 +555,14 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
             const T sc = T(1.0 / hprev);
             T* vh = w.V + (long long)have * w.ldv;
             for (int r = rb + tid; r < re; r += BLOCK) vh[r] = T(ys[r] * sc);
+            if (tm.rank == 0 && tid == 0) st->bytes += 2.0 * sizeof(T) * n;
           }
         }
-        if (tm.rank == 0) decide<T>(P, w, have, broke, sh);
+        if (tm.rank == 0) {
+          DecideArgs da{P.tol, P.tau_fixed, (double)P.nnz, (double)n, P.max_attempts,
+                        p, P.adapt_m, P.corrector, have, broke ? 1 : 0};
+          decide(da, st, w.H, w.ex);
+        }
         if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
         if (!st->accept) {
           if (st->done) goto finish;  // attempt limit
@@ -561,6 +584,9 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
           }
           P.u[r] = s;
         }
+        if (tm.rank == 0 && tid == 0)
+          st->bytes += 8.0 * n * (p > 0 ? p + 1.0 : 1.0) +
+                       (use_v ? (mu + (use_corr ? 1.0 : 0.0)) * sizeof(T) * (double)n : 0.0);
         if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
         break;
       }
@@ -582,6 +608,7 @@ finish:
     o->workgroups = tm.size;
     o->anorm = st->anorm;
     o->setup_flags = st->setup_flags;
+    o->bytes = st->bytes;
   }
 }
 
