@@ -21,6 +21,9 @@ FLAGS = [
     "-Werror=return-type",
     # keep packed-FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # per-lane LDS atomics (pivot search) stay per-lane instead of becoming a
+    # scalar loop over the active lanes
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -9,10 +9,59 @@
 
 namespace pkr {
 
-// C = A B for N x N row-major matrices; one output entry per thread.
+constexpr int DENSE_LDS = 9340;  // doubles of LDS available to the dense routines
+
+// C = A B for N x N row-major matrices in device memory (an L2-resident
+// scratch).  When both operands fit, A is staged transposed and B as is in
+// LDS, zero-padded to a multiple of 4, and every thread accumulates a 4 x 4
+// block of C in registers from 16-byte LDS reads; otherwise one output entry
+// per thread straight from memory.
 __device__ __forceinline__ void wg_matmul(int N, const double* __restrict__ A,
-                                          const double* __restrict__ B, double* __restrict__ C) {
+                                          const double* __restrict__ B, double* __restrict__ C,
+                                          double* L) {
   const int NN = N * N;
+  const int N4 = (N + 3) & ~3;
+  if (2 * N4 * N4 <= DENSE_LDS) {
+    double* At = L;             // At[k][i] = A[i][k]
+    double* Bs = L + N4 * N4;   // Bs[k][j] = B[k][j]
+    for (int e = threadIdx.x; e < N4 * N4; e += BLOCK) {
+      const int r = e / N4, c = e - r * N4;
+      const bool in = r < N && c < N;
+      At[c * N4 + r] = in ? A[r * N + c] : 0.0;
+      Bs[e] = in ? B[r * N + c] : 0.0;
+    }
+    __syncthreads();
+    const int nb = N4 >> 2;
+    for (int t = threadIdx.x; t < nb * nb; t += BLOCK) {
+      const int ib = t / nb, jb = t - ib * nb;
+      const int i0 = 4 * ib, j0 = 4 * jb;
+      double c[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c[a][b] = 0.0;
+#pragma unroll 4
+      for (int k = 0; k < N; ++k) {
+        const double2 x01 = *reinterpret_cast<const double2*>(At + k * N4 + i0);
+        const double2 x23 = *reinterpret_cast<const double2*>(At + k * N4 + i0 + 2);
+        const double2 y01 = *reinterpret_cast<const double2*>(Bs + k * N4 + j0);
+        const double2 y23 = *reinterpret_cast<const double2*>(Bs + k * N4 + j0 + 2);
+        const double x[4] = {x01.x, x01.y, x23.x, x23.y};
+        const double y[4] = {y01.x, y01.y, y23.x, y23.y};
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) c[a][b] = fma(x[a], y[b], c[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (i0 + a < N && j0 + b < N) C[(i0 + a) * N + j0 + b] = c[a][b];
+    }
+    __syncthreads();
+    return;
+  }
   for (int e = threadIdx.x; e < NN; e += BLOCK) {
     const int i = e / N, j = e - i * N;
     const double* a = A + i * N;
@@ -24,13 +73,78 @@ __device__ __forceinline__ void wg_matmul(int N, const double* __restrict__ A,
   __syncthreads();
 }
 
-// Solve P X = Q in place (X overwrites Q) by Gauss-Jordan with row pivoting.
-__device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q) {
-  __shared__ double s_fac[NMAX_EXPM];
-  __shared__ int s_piv;
+// Pivot key: |v| as a float with the 8 low mantissa bits replaced by
+// 255 - row, so that an unsigned max picks the largest |v| (to 2^-15
+// relative) and, among equals, the smallest row.  Needs N <= 256.
+__device__ __forceinline__ unsigned pivot_key(double v, int row) {
+  const unsigned f = __float_as_uint((float)fabs(v));
+  return (f & 0xffffff00u) | (255u - (unsigned)row);
+}
+
+// Solve P X = Q in place (X overwrites Q) by Gauss-Jordan elimination with
+// partial pivoting.  When [P | Q] fits in LDS (N <= 128), stored by columns,
+// lanes own rows (i and i+64) and waves own columns, so every column is
+// updated by a single wave: the pivot row and row k are read in place (LDS
+// operations of one wave complete in order) and the row exchange is folded
+// into the update.  Wave 0, which owns column k+1, posts the candidates for
+// the next pivot with LDS atomic max on pivot keys.  One barrier per column.
+__device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q, double* L) {
+  __shared__ unsigned s_key[2];
   const int tid = threadIdx.x;
+  const int lane = tid % WAVE, wv = tid / WAVE;
+  const int W2 = 2 * N;
+  const int ld = (N + 1) & ~1;  // column stride of the transposed system
+  if (N <= 2 * WAVE && W2 * ld <= DENSE_LDS) {
+    double* M = L;  // [P | Q] stored by columns: entry (i, j) at M[j * ld + i]
+    if (tid == 0) { s_key[0] = 0u; s_key[1] = 0u; }
+    for (int e = tid; e < N * N; e += BLOCK) {
+      const int i = e / N, j = e - i * N;
+      M[j * ld + i] = P[e];
+      M[(N + j) * ld + i] = Q[e];
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += BLOCK) atomicMax(&s_key[0], pivot_key(M[i], i));
+    __syncthreads();
+    const int i0 = lane, i1 = lane + WAVE;
+    const bool r0 = i0 < N, r1 = i1 < N;
+    for (int k = 0; k < N; ++k) {
+      const int piv = 255 - (int)(s_key[k & 1] & 0xffu);
+      if (tid == 0) s_key[(k + 1) & 1] = 0u;
+      const double* colk = M + k * ld;
+      const double inv = 1.0 / colk[piv];
+      const double kk = colk[k];
+      const double f0 = r0 ? colk[i0] : 0.0;
+      const double f1 = r1 ? colk[i1] : 0.0;
+#pragma unroll 4
+      for (int j = k + 1 + wv; j < W2; j += NWAVES) {
+        double* col = M + j * ld;
+        const double pr = col[piv] * inv;
+        const double kj = col[k];
+        const double a0 = r0 ? col[i0] : 0.0;
+        const double a1 = r1 ? col[i1] : 0.0;
+        const double v0 = i0 == k ? pr : (i0 == piv ? kj - kk * pr : a0 - f0 * pr);
+        const double v1 = i1 == k ? pr : (i1 == piv ? kj - kk * pr : a1 - f1 * pr);
+        if (j == k + 1 && j < N) {  // candidates for the next pivot: rows > k
+          if (r0 && i0 > k) atomicMax(&s_key[(k + 1) & 1], pivot_key(v0, i0));
+          if (r1 && i1 > k) atomicMax(&s_key[(k + 1) & 1], pivot_key(v1, i1));
+        }
+        if (r0) col[i0] = v0;
+        if (r1) col[i1] = v1;
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < N * N; e += BLOCK) {
+      const int i = e / N, j = e - i * N;
+      Q[e] = M[(N + j) * ld + i];
+    }
+    __syncthreads();
+    return;
+  }
+  __shared__ int s_pivg;
+  // large systems: the same elimination on the matrices in device memory
+  __shared__ double s_fac[NMAX_EXPM];
   for (int k = 0; k < N; ++k) {
-    if (tid < WAVE) {  // one wave finds the pivot row
+    if (tid < WAVE) {
       double best = -1.0;
       int bi = k;
       for (int i = k + tid; i < N; i += WAVE) {
@@ -42,10 +156,10 @@ __device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q) {
         int oi = __shfl_xor(bi, off, WAVE);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
-      if (tid == 0) s_piv = bi;
+      if (tid == 0) s_pivg = bi;
     }
     __syncthreads();
-    const int piv = s_piv;
+    const int piv = s_pivg;
     if (piv != k) {
       for (int j = tid; j < 2 * N; j += BLOCK) {
         double* M = j < N ? P : Q;
@@ -56,18 +170,15 @@ __device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q) {
       }
       __syncthreads();
     }
-    // factors of column k (the pivot entry becomes the reciprocal)
     for (int i = tid; i < N; i += BLOCK) s_fac[i] = P[i * N + k];
     __syncthreads();
     const double inv = 1.0 / s_fac[k];
-    // scale the pivot row
     for (int j = tid; j < 2 * N; j += BLOCK) {
       if (j < N) { if (j > k) P[k * N + j] *= inv; }
       else Q[k * N + (j - N)] *= inv;
     }
     __syncthreads();
-    // eliminate column k from every other row
-    const int W = (N - k - 1) + N;  // columns k+1..N-1 of P, all of Q
+    const int W = (N - k - 1) + N;
     for (int e = tid; e < N * W; e += BLOCK) {
       const int i = e / W;
       if (i == k) continue;
@@ -87,9 +198,11 @@ __device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q) {
 }
 
 // E = exp(A) for the N x N matrix in S[0] (overwritten).  S must hold 8
-// matrices of N*N doubles.  Returns (in shared out_*) the 1-norm of A and the
-// number of squarings.  The result is in the returned pointer (inside S).
-__device__ __forceinline__ double* wg_expm(int N, double* S, double* out_norm1, int* out_s) {
+// matrices of N*N doubles; L is DENSE_LDS doubles of shared memory.  Returns
+// (in shared out_*) the 1-norm of A and the number of squarings.  The result
+// is in the returned pointer (inside S).
+__device__ __forceinline__ double* wg_expm(int N, double* S, double* L, double* out_norm1,
+                                           int* out_s) {
   __shared__ double s_norm;
   __shared__ double s_c[14];
   const int tid = threadIdx.x;
@@ -130,20 +243,20 @@ __device__ __forceinline__ double* wg_expm(int N, double* S, double* out_norm1, 
   __syncthreads();
   const double* c = s_c;
 
-  wg_matmul(N, X, X, X2);
-  wg_matmul(N, X2, X2, X4);
-  wg_matmul(N, X4, X2, X6);
+  wg_matmul(N, X, X, X2, L);
+  wg_matmul(N, X2, X2, X4, L);
+  wg_matmul(N, X4, X2, X6, L);
   for (size_t e = tid; e < NN; e += BLOCK) T[e] = c[13] * X6[e] + c[11] * X4[e] + c[9] * X2[e];
   __syncthreads();
-  wg_matmul(N, X6, T, U1);
+  wg_matmul(N, X6, T, U1, L);
   for (size_t e = tid; e < NN; e += BLOCK) {
     const int i = (int)(e / N), j = (int)(e - (size_t)i * N);
     U1[e] += c[7] * X6[e] + c[5] * X4[e] + c[3] * X2[e] + (i == j ? c[1] : 0.0);
     T[e] = c[12] * X6[e] + c[10] * X4[e] + c[8] * X2[e];
   }
   __syncthreads();
-  wg_matmul(N, X, U1, U);       // odd part
-  wg_matmul(N, X6, T, Vv);      // even part (before the low-order terms)
+  wg_matmul(N, X, U1, U, L);    // odd part
+  wg_matmul(N, X6, T, Vv, L);   // even part (before the low-order terms)
   double* P = T;
   double* Q = U1;
   for (size_t e = tid; e < NN; e += BLOCK) {
@@ -153,11 +266,11 @@ __device__ __forceinline__ double* wg_expm(int N, double* S, double* out_norm1, 
     Q[e] = ev + U[e];
   }
   __syncthreads();
-  wg_gauss_jordan(N, P, Q);
+  wg_gauss_jordan(N, P, Q, L);
   double* cur = Q;
   double* nxt = U;
   for (int k = 0; k < s; ++k) {
-    wg_matmul(N, cur, cur, nxt);
+    wg_matmul(N, cur, cur, nxt, L);
     double* t = cur; cur = nxt; nxt = t;
   }
   if (tid == 0) { *out_norm1 = nrm; *out_s = s; }

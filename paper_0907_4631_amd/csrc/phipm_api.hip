@@ -47,9 +47,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int n, const int* rp, const int*
 __global__ __launch_bounds__(BLOCK) void k_expm(int N, const double* H, double* E, double* S) {
   __shared__ double s_norm;
   __shared__ int s_sq;
+  __shared__ double L[DENSE_LDS];
   for (int e = threadIdx.x; e < N * N; e += BLOCK) S[e] = H[e];
   __syncthreads();
-  const double* R = wg_expm(N, S, &s_norm, &s_sq);
+  const double* R = wg_expm(N, S, L, &s_norm, &s_sq);
   for (int e = threadIdx.x; e < N * N; e += BLOCK) E[e] = R[e];
 }
 

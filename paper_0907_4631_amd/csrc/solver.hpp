@@ -93,6 +93,7 @@ struct Shared {
   union {
     SpmvSmem<double> sm64;
     SpmvSmem<float> sm32;
+    double dense[DENSE_LDS];  // workgroup 0's small-matrix work
   };
   double blk[KMAX];
   double red[KMAX];
@@ -230,7 +231,8 @@ struct DecideArgs {
 // Workgroup 0: exponential of the augmented matrix, error estimate and the
 // decisions of Algorithms 3 and 4 for one attempt.  Kept out of line: it is
 // cold code with high register pressure.
-__device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, double* ex) {
+__device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, double* ex,
+                                   double* L) {
   __shared__ double s_c, s_norm;
   __shared__ int s_sq;
   const int p = a.p;
@@ -255,7 +257,7 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       K[e] = v;
     }
     __syncthreads();
-    const double* E = wg_expm(N, ex, &s_norm, &s_sq);
+    const double* E = wg_expm(N, ex, L, &s_norm, &s_sq);
     const int col = p == 0 ? 0 : m_use + p - 1;
     for (int k = threadIdx.x; k < m_use; k += BLOCK) st->yb[k] = beta * E[(long long)k * N + col];
     if (threadIdx.x == 0) s_c = E[(long long)(m_use - 1) * N + m_use + p];
@@ -561,7 +563,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
         if (tm.rank == 0) {
           DecideArgs da{P.tol, P.tau_fixed, (double)P.nnz, (double)n, P.max_attempts,
                         p, P.adapt_m, P.corrector, have, broke ? 1 : 0};
-          decide(da, st, w.H, w.ex);
+          decide(da, st, w.H, w.ex, sh.dense);
         }
         if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
         if (!st->accept) {
