@@ -9,7 +9,7 @@
 
 namespace pkr {
 
-constexpr int DENSE_LDS = 9340;  // doubles of LDS available to the dense routines
+constexpr int DENSE_LDS = 17408;  // doubles of LDS available to the dense routines
 
 // C = A B for N x N row-major matrices in device memory (an L2-resident
 // scratch).  When both operands fit, A is staged transposed and B as is in

@@ -21,10 +21,9 @@ __global__ void k_zero_ctl(TeamCtl* ctl, int count) {
   for (size_t i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0u;
 }
 
-// At most 128 VGPRs, so that two 512-thread workgroups share a CU (the
-// streaming phases need the extra waves in flight).
+// One 1024-thread workgroup per CU (16 waves, at most 128 VGPRs each).
 template <typename T>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_solve(Problem P, Work<T> w, TeamCtl* ctl,
+__global__ __launch_bounds__(BLOCK) void k_solve(Problem P, Work<T> w, TeamCtl* ctl,
                                                  double* partials, double* result,
                                                  unsigned long long spin) {
   __shared__ Shared sh;
@@ -284,7 +283,7 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   unsigned long long spin = d->spin_ticks;
   const int G = choose_workgroups(o, A->n, gmax);
 
-  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, stream, ctl, 1);
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1);
   if (hipGetLastError() != hipSuccess) return fail(PHIPM_EHIP);
   hipError_t e;
   if (fp32) {
@@ -395,7 +394,7 @@ int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double
   phipm_opts o;
   phipm_default_opts(&o);
   const int G = choose_workgroups(&o, A->n, d->coresident64);
-  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, stream, ctl, 1);
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1);
   void* args[] = {&P, &w, &v, &m, &lanczos, &H, &dm, &ctl, &part, &res, &spin};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_krylov), dim3(G), dim3(BLOCK),
                                  args, 0, stream) != hipSuccess)

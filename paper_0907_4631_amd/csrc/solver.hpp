@@ -94,6 +94,7 @@ struct Shared {
     SpmvSmem<double> sm64;
     SpmvSmem<float> sm32;
     double dense[DENSE_LDS];  // workgroup 0's small-matrix work
+    double wpart[NWAVES][KMAX];  // per-wave partial dot products (phase_dots)
   };
   double blk[KMAX];
   double red[KMAX];
@@ -130,11 +131,14 @@ template <>
 __device__ __forceinline__ SpmvSmem<float>& smem_for<float>(Shared& sh) { return sh.sm32; }
 
 // blk[k] = sum over own rows of V[:, i0+k] . y for k < K (block-reduced, float64).
+// Columns are taken 8 at a time; each wave reduces its partial sums with DPP
+// and parks them in LDS, and the waves' sums are added in wave order after a
+// single barrier.
 template <typename T>
-__device__ __forceinline__ void phase_dots(const T* V, long long ldv, int i0, int K, const T* y, int rb, int re,
-                           Shared& sh) {
+__device__ __forceinline__ void phase_dots(const T* V, long long ldv, int i0, int K, const T* y,
+                                           int rb, int re, Shared& sh) {
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   for (int g = 0; g < K; g += 8) {
-    double acc[8];
     T a[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) a[q] = T(0);
@@ -146,9 +150,20 @@ __device__ __forceinline__ void phase_dots(const T* V, long long ldv, int i0, in
         if (q < kk) a[q] += V[(long long)(i0 + g + q) * ldv + r] * yr;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = (double)a[q];
-    block_reduce<8>(acc, RED_SUM, sh.blk + g);
+    for (int q = 0; q < 8; ++q) {
+      if (q < kk) {
+        const double t = wave_sum((double)a[q]);
+        if (lane == 0) sh.wpart[wv][g + q] = t;
+      }
+    }
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    double t = sh.wpart[0][k];
+    for (int w2 = 1; w2 < NWAVES; ++w2) t += sh.wpart[w2][k];
+    sh.blk[k] = t;
+  }
+  __syncthreads();
 }
 
 // y -= V[:, i0..i0+K) h over own rows.

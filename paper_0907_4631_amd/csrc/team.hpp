@@ -8,7 +8,7 @@
 
 namespace pkr {
 
-constexpr int BLOCK = 512;               // threads per workgroup
+constexpr int BLOCK = 1024;              // threads per workgroup (one per CU)
 constexpr int WAVE = 64;                 // CDNA wavefront
 constexpr int NWAVES = BLOCK / WAVE;
 constexpr int M_CAP = 128;               // largest Krylov dimension
@@ -19,17 +19,20 @@ constexpr int NMAX_EXPM = M_CAP + P_MAX + 1;
 constexpr int TEAM_GROUP = 16;            // workgroups per arrival group
 constexpr int TEAM_MAX = 1024;            // largest team
 constexpr int TEAM_NGROUPS = TEAM_MAX / TEAM_GROUP;
+constexpr int FLAG_STRIDE = 32;           // one flag per 128-byte line
 
-// Team control block in device memory.  Arrivals are counted per group of
-// TEAM_GROUP workgroups (each counter on its own 128-byte line); the last
-// arrival of a group then arrives at the top counter.  This keeps the number
-// of serialized atomics on any one address at TEAM_GROUP or the group count.
+// Team control block in device memory (zeroed before every launch).  Every
+// workgroup posts the epoch it reached in its own flag; the first workgroup
+// of each group of TEAM_GROUP (the group leader) waits for its members'
+// flags, and workgroup 0 waits for the group leaders' flags and then
+// publishes the generation.  There are no read-modify-write atomics, so
+// nothing serializes on one address.
 struct TeamCtl {
-  unsigned count;    // group arrivals at the top in the current generation
-  unsigned gen;      // generation number
+  unsigned gen;      // generation number (last completed barrier)
   unsigned abort;    // set when a wait exceeded its time budget
-  unsigned pad[29];
-  unsigned grp[TEAM_NGROUPS][32];  // per-group arrival counters
+  unsigned pad[FLAG_STRIDE - 2];
+  unsigned garr[TEAM_NGROUPS][FLAG_STRIDE];  // group leaders' epochs
+  unsigned arr[TEAM_MAX][FLAG_STRIDE];       // members' epochs
 };
 
 struct Team {
@@ -49,16 +52,44 @@ __device__ __forceinline__ double nanmax(double a, double b) {
   return a > b ? a : b;
 }
 
+// Move a double between lanes with a DPP pattern (row_mask/bank_mask
+// select the rows/banks written; other lanes keep `old`).
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ double dpp(double old, double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL,
+                                             ROW_MASK, BANK_MASK, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL,
+                                             ROW_MASK, BANK_MASK, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave-wide sum / max with DPP: quad swaps, half-row and row mirrors, then
+// the row broadcasts 15 and 31; the total ends in lane 63 and is returned to
+// every lane.  Fixed order of operations.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
+  v += dpp<0xB1>(0.0, v);                 // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(0.0, v);                 // quad_perm [2,3,0,1]
+  v += dpp<0x141>(0.0, v);                // row_half_mirror
+  v += dpp<0x140>(0.0, v);                // row_mirror: row sums in every lane
+  v += dpp<0x142, 0xa>(0.0, v);           // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xc>(0.0, v);           // row_bcast:31 into rows 2 and 3
+  return lane_value(v, 63);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, WAVE));
-  return v;
+  v = nanmax(v, dpp<0xB1>(v, v));
+  v = nanmax(v, dpp<0x4E>(v, v));
+  v = nanmax(v, dpp<0x141>(v, v));
+  v = nanmax(v, dpp<0x140>(v, v));
+  v = nanmax(v, dpp<0x142, 0xa>(v, v));
+  v = nanmax(v, dpp<0x143, 0xc>(v, v));
+  return lane_value(v, 63);
 }
 
 // Block-wide reduction of KB values held by every thread; the result lands in
@@ -98,11 +129,7 @@ __device__ __forceinline__ void st_relaxed(unsigned* p, unsigned v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ unsigned add_relaxed(unsigned* p, unsigned v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Reduce src[0..cnt) (stride 1) for K rows of length ld, writing dst[k*dld+di].
+// Reduce src rows: dst[k*dld+di] = op over src[k*ld + 0..cnt) for k < K.
 __device__ __forceinline__ void reduce_rows(const double* src, int ld, int cnt, int K, int op,
                                             double* dst, int dld, int di) {
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
@@ -115,17 +142,39 @@ __device__ __forceinline__ void reduce_rows(const double* src, int ld, int cnt, 
   }
 }
 
+// Wave 0 of the calling workgroup waits until flags[base .. base+cnt) (cnt <=
+// 64, one per lane, FLAG_STRIDE apart) have all reached epoch e.  Returns 0
+// if the team was aborted or the wait ran out of time (then sets abort).
+__device__ __forceinline__ int wait_flags(const Team& tm, unsigned* flags, int cnt, unsigned e) {
+  const int lane = threadIdx.x % WAVE;
+  const uint64_t t0 = wall_clock64();
+  int ok = 1;
+  int all = 0;
+  while (ok && !all) {
+    const unsigned f = lane < cnt ? ld_relaxed(flags + (size_t)lane * FLAG_STRIDE) : e;
+    all = __all((int)(f - e) >= 0);
+    if (!all) {
+      __builtin_amdgcn_s_sleep(1);
+      if (ld_relaxed(&tm.ctl->abort)) ok = 0;
+      else if (wall_clock64() - t0 > tm.spin_ticks) {
+        st_relaxed(&tm.ctl->abort, 1u);
+        ok = 0;
+      }
+    }
+  }
+  return ok;
+}
+
 // Synchronise the team and reduce K per-workgroup values.  blk (shared memory)
 // holds this workgroup's K values; on return out (shared memory) holds the
 // team-wide reduction, identical in every workgroup.  K = 0 is a plain
-// barrier.  The last arrival of each group sums that group's values (in rank
-// order), the last group to arrive sums the group sums (in group order), so
-// the result does not depend on arrival order.  Waiters poll the generation
-// word with relaxed loads and acquire once.  Returns false if the team was
-// aborted (a wait ran past its time budget); callers then leave the kernel.
+// barrier.  Group leaders sum their group's values in rank order and
+// workgroup 0 sums the group sums in group order, so the result does not
+// depend on timing.  Returns false if the team was aborted (a wait ran past
+// its time budget); callers then leave the kernel.
 __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int K, int op,
                                           double* out) {
-  __shared__ int s_role;  // 0 = waiter, 1 = last of its group, 2 = last overall
+  __shared__ unsigned s_epoch;
   __shared__ int s_ok;
   const int tid = threadIdx.x;
   if (tm.size == 1) {
@@ -138,44 +187,57 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
   const int grp = tm.rank / TEAM_GROUP;
   const int g0 = grp * TEAM_GROUP;
   const int gsz = tm.size - g0 < TEAM_GROUP ? tm.size - g0 : TEAM_GROUP;
+  const bool leader = tm.rank == g0;
   double* gsum = tm.partials + (size_t)KMAX * tm.size;  // [KMAX][ngroups]
   for (int k = tid; k < K; k += BLOCK) tm.partials[(size_t)k * tm.size + tm.rank] = blk[k];
   __syncthreads();
-  unsigned g = 0;
   if (tid == 0) {
-    g = ld_relaxed(&tm.ctl->gen);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned old = add_relaxed(&tm.ctl->grp[grp][0], 1u);
-    s_role = (old == (unsigned)gsz - 1u) ? 1 : 0;
+    const unsigned e = ld_relaxed(&tm.ctl->gen) + 1u;
+    s_epoch = e;
     s_ok = 1;
-    if (s_role) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    st_relaxed(&tm.ctl->arr[tm.rank][0], e);
   }
   __syncthreads();
-  if (s_role) {
+  const unsigned e = s_epoch;
+  if (leader) {
+    if (tid < WAVE) {
+      const int ok = wait_flags(tm, &tm.ctl->arr[g0][0], gsz, e);
+      if (tid == 0) {
+        s_ok = ok;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+    }
+    __syncthreads();
+    if (!s_ok) return false;
     reduce_rows(tm.partials + g0, tm.size, gsz, K, op, gsum, ngroups, grp);
     __syncthreads();
     if (tid == 0) {
-      st_relaxed(&tm.ctl->grp[grp][0], 0u);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const unsigned old = add_relaxed(&tm.ctl->count, 1u);
-      s_role = (old == (unsigned)ngroups - 1u) ? 2 : 1;
-      if (s_role == 2) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      st_relaxed(&tm.ctl->garr[grp][0], e);
     }
-    __syncthreads();
-    if (s_role == 2) {
+    if (tm.rank == 0) {
+      if (tid < WAVE) {
+        const int ok = wait_flags(tm, &tm.ctl->garr[0][0], ngroups, e);
+        if (tid == 0) {
+          s_ok = ok;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+      }
+      __syncthreads();
+      if (!s_ok) return false;
       reduce_rows(gsum, ngroups, ngroups, K, op, tm.result, 1, 0);
       __syncthreads();
       if (tid == 0) {
-        st_relaxed(&tm.ctl->count, 0u);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        st_relaxed(&tm.ctl->gen, g + 1u);
+        st_relaxed(&tm.ctl->gen, e);
       }
     }
   }
-  if (s_role != 2 && tid == 0) {
+  if (tm.rank != 0 && tid == 0) {
     const uint64_t t0 = wall_clock64();
     int ok = 1;
-    while (ok && ld_relaxed(&tm.ctl->gen) == g) {
+    while (ok && (int)(ld_relaxed(&tm.ctl->gen) - e) < 0) {
       __builtin_amdgcn_s_sleep(1);
       if (ld_relaxed(&tm.ctl->abort)) ok = 0;
       else if (wall_clock64() - t0 > tm.spin_ticks) {
