@@ -190,7 +190,7 @@ bool csr_ok(const phipm_csr* A) {
 int choose_workgroups(const phipm_opts* o, int n, int gmax) {
   int g = o->workgroups;
   if (g <= 0) {
-    long long want = ((long long)n + 2047) / 2048;
+    long long want = ((long long)n + 1023) / 1024;
     g = (int)std::min<long long>(want, gmax);
   }
   if (g > gmax) g = gmax;
