@@ -94,6 +94,8 @@ typedef struct {
   int32_t pad_;
   double bytes;      /* algorithmic HBM bytes of the streaming phases: every CSR array,
                         basis column and vector counted once per pass that touches it */
+  double phi_ratio_max;        /* FP32 basis: largest ||beta y||_2 / ||u_k||_2 of a step */
+  int64_t precision_rejects;   /* FP32 basis: attempts rejected for basis rounding */
 } phipm_stats;
 
 void phipm_default_opts(phipm_opts* opts);

@@ -44,7 +44,8 @@ class Stats(C.Structure):
                 ("expms", C.c_int64), ("t_reached", C.c_double), ("tau_last", C.c_double),
                 ("m_last", C.c_int32), ("status", C.c_int32), ("lanczos", C.c_int32),
                 ("workgroups", C.c_int32), ("anorm", C.c_double), ("setup_flags", C.c_int32),
-                ("pad_", C.c_int32), ("bytes", C.c_double)]
+                ("pad_", C.c_int32), ("bytes", C.c_double), ("phi_ratio_max", C.c_double),
+                ("precision_rejects", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

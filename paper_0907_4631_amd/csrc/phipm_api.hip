@@ -329,6 +329,8 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
     stats->setup_flags = hs.setup_flags;
     stats->pad_ = 0;
     stats->bytes = hs.bytes;
+    stats->phi_ratio_max = hs.rho_max;
+    stats->precision_rejects = hs.prec_rejects;
     return stats->status;
   }
   return PHIPM_OK;

@@ -57,12 +57,17 @@ struct Stats {              // mirrors phipm_stats
   double anorm;
   int setup_flags, pad;
   double bytes;
+  double rho_max;
+  long long prec_rejects;
 };
 
 struct State {
   double t_end, sgn, anorm, bnorm, bd_tol;
   double t, tau, beta;
   double bytes;             // algorithmic HBM bytes so far
+  double unorm;             // ||u_k||_2 of the current state
+  double rho_max;           // largest ||beta y|| / ||u_k|| seen (FP32 basis)
+  long long prec_rejects;   // attempts rejected for FP32 rounding
   int setup_flags, pad0;
   double eps, omega, knorm;
   int m, m_cap, lanczos, zero_path;
@@ -139,15 +144,15 @@ __device__ __forceinline__ void phase_dots(const T* V, long long ldv, int i0, in
                                            int rb, int re, Shared& sh) {
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   for (int g = 0; g < K; g += 8) {
-    T a[8];
+    double a[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] = T(0);
+    for (int q = 0; q < 8; ++q) a[q] = 0.0;
     const int kk = K - g < 8 ? K - g : 8;
     for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
-      const T yr = y[r];
+      const double yr = (double)y[r];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q < kk) a[q] += V[(long long)(i0 + g + q) * ldv + r] * yr;
+        if (q < kk) a[q] += (double)V[(long long)(i0 + g + q) * ldv + r] * yr;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -171,9 +176,9 @@ template <typename T>
 __device__ __forceinline__ void phase_project(const T* V, long long ldv, int i0, int K, const double* h, T* y,
                               int rb, int re) {
   for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
-    T yr = y[r];
-    for (int k = 0; k < K; ++k) yr -= T(h[k]) * V[(long long)(i0 + k) * ldv + r];
-    y[r] = yr;
+    double yr = (double)y[r];
+    for (int k = 0; k < K; ++k) yr -= h[k] * (double)V[(long long)(i0 + k) * ldv + r];
+    y[r] = T(yr);
   }
 }
 
@@ -188,13 +193,17 @@ __device__ __forceinline__ double krylov_step(const Team& tm, const Problem& P, 
   T* y = (j & 1) ? w.y1 : w.y0;
   T* vj = w.V + (long long)j * w.ldv;
   auto vload = [&](int c) -> T { return T(src[c] * scale); };
+  // values and basis are stored as T; products and sums are formed in FP64
+  // (a float times a float is exact in double), so the FP32 basis does not
+  // lose digits to the cancellation inside stiff stencil rows
+  auto vload64 = [&](int c) -> double { return (double)vload(c); };
   // P1: y = A v_j
   for (int r0 = rb; r0 < re; r0 += BLOCK) {
     const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
-    T acc = spmv_tile<T, T>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), vload);
+    const double acc = spmv_tile<T, double>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), vload64);
     const int r = r0 + threadIdx.x;
     if (r < r1) {
-      y[r] = T(sgn) * acc;
+      y[r] = T(sgn * acc);
       vj[r] = vload(r);
     }
   }
@@ -211,9 +220,9 @@ __device__ __forceinline__ double krylov_step(const Team& tm, const Problem& P, 
   phase_project<T>(w.V, w.ldv, i0, K, sh.red, y, rb, re);
   {
     double acc[1];
-    T a = T(0);
-    for (int r = rb + threadIdx.x; r < re; r += BLOCK) a += y[r] * y[r];
-    acc[0] = (double)a;
+    double a = 0.0;
+    for (int r = rb + threadIdx.x; r < re; r += BLOCK) a += (double)y[r] * (double)y[r];
+    acc[0] = a;
     if (tm.rank == 0) {
       // workgroup 0 records column j of H (it alone reads H)
       for (int i = threadIdx.x; i <= M_CAP; i += BLOCK) {
@@ -240,8 +249,11 @@ __device__ __forceinline__ double krylov_step(const Team& tm, const Problem& P, 
 struct DecideArgs {
   double tol, tau_fixed, nnz, n;
   long long max_attempts;
-  int p, adapt_m, corrector, have, broke;
+  int p, adapt_m, corrector, have, broke, fp32;
 };
+
+// Unit roundoff of the FP32 basis.
+constexpr double EPS32 = 5.9604644775390625e-08;
 
 // Workgroup 0: exponential of the augmented matrix, error estimate and the
 // decisions of Algorithms 3 and 4 for one attempt.  Kept out of line: it is
@@ -332,6 +344,38 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       mem.tau = tau;
       mem.m = m_use;
       mem.rejected = !accept;
+    }
+    // FP32 basis: the phi-part beta*V*y is added to the Taylor part of eq. step
+    // and may be rho = ||beta y|| / ||u_k|| times larger than the result.  Its
+    // FP32 error is about EPS32 * rho * max(1, ||tau K||_1): the basis and the
+    // entries of H carry FP32 rounding, and the exponential amplifies a
+    // relative change of tau H by up to ||tau H||.  That must fit the step's
+    // share of the relative budget, 5 tol sqrt(tau / t_end).  When the
+    // phi-part dominates (rho > 4) and the rounding does not fit, the attempt
+    // is rejected and tau shrunk (the Krylov basis does not depend on tau); on
+    // acceptance the same bound caps the next tau.  With rho = O(1) FP32 is at
+    // its floor and a smaller tau would not help.
+    if (a.fp32 && beta > 0.0 && !(a.tau_fixed > 0.0) && isfinite(omega)) {
+      double ys = 0.0;
+      for (int k = 0; k < m_use; ++k) ys += st->yb[k] * st->yb[k];
+      const double rho = sqrt(ys) / (st->unorm > 0.0 ? st->unorm : 1.0);
+      if (rho > st->rho_max) st->rho_max = rho;
+      if (rho > 4.0) {
+        const double est = EPS32 * rho * (knorm > 1.0 ? knorm : 1.0);
+        const double allow = 5.0 * a.tol * sqrt(tau / t_end);
+        const double f = pow(allow / est, 1.0 / (double)(p + 1));
+        double tcap = tau * (f < 0.2 ? 0.2 : 0.9 * f);
+        if (est > allow && accept) {
+          accept = 0;
+          st->prec_rejects += 1;
+          tau_next = tcap < tau_next ? tcap : tau_next;
+          m_next = m_use;
+          mem.rejected = 1;
+          mem.branch = 1;
+        } else if (tcap < tau_next) {
+          tau_next = tcap;
+        }
+      }
     }
     st->eps = eps;
     st->omega = omega;
@@ -467,6 +511,9 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
       st->tau_last = 0.0;
       st->m_last = 0;
       st->mem = Alg4Mem{};
+      st->rho_max = 0.0;
+      st->prec_rejects = 0;
+      st->unorm = 0.0;
       st->bytes = (check_sym ? 24.0 : 12.0) * P.nnz + 4.0 * (n + 1.0) + 8.0 * n * (p + 1.0) +
                   (fp32 ? 4.0 * P.nnz : 0.0);
     }
@@ -490,9 +537,18 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
     goto finish;
   }
 
-  for (int r = rb + tid; r < re; r += BLOCK) P.u[r] = P.b[r];
-  if (tm.rank == 0 && tid == 0) st->bytes += 16.0 * n;
-  if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+  {
+    double a1[1] = {0.0};
+    for (int r = rb + tid; r < re; r += BLOCK) {
+      const double v = P.b[r];
+      P.u[r] = v;
+      a1[0] += v * v;
+    }
+    if (tm.rank == 0 && tid == 0) st->bytes += 16.0 * n;
+    block_reduce<1>(a1, RED_SUM, sh.blk);
+    if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+    if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
+  }
 
   {
     const T* valT;
@@ -577,7 +633,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
         }
         if (tm.rank == 0) {
           DecideArgs da{P.tol, P.tau_fixed, (double)P.nnz, (double)n, P.max_attempts,
-                        p, P.adapt_m, P.corrector, have, broke ? 1 : 0};
+                        p, P.adapt_m, P.corrector, have, broke ? 1 : 0, fp32 ? 1 : 0};
           decide(da, st, w.H, w.ex, sh.dense);
         }
         if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
@@ -592,6 +648,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
         __syncthreads();
         const bool use_v = beta > 0.0;
         const bool use_corr = use_v && sh.yb[mu] != 0.0;
+        double un[1] = {0.0};
         for (int r = rb + tid; r < re; r += BLOCK) {
           double s = p > 0 ? sh.coef[0] * P.u[r] : 0.0;
           for (int j = 1; j < p; ++j) s += sh.coef[j] * w.W[(long long)(j - 1) * w.ldw + r];
@@ -600,11 +657,14 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
             if (use_corr) s += sh.yb[mu] * (double)w.V[(long long)mu * w.ldv + r];
           }
           P.u[r] = s;
+          un[0] += s * s;
         }
         if (tm.rank == 0 && tid == 0)
           st->bytes += 8.0 * n * (p > 0 ? p + 1.0 : 1.0) +
                        (use_v ? (mu + (use_corr ? 1.0 : 0.0)) * sizeof(T) * (double)n : 0.0);
-        if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+        block_reduce<1>(un, RED_SUM, sh.blk);
+        if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+        if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
         break;
       }
     }
@@ -626,6 +686,8 @@ finish:
     o->anorm = st->anorm;
     o->setup_flags = st->setup_flags;
     o->bytes = st->bytes;
+    o->rho_max = st->rho_max;
+    o->prec_rejects = st->prec_rejects;
   }
 }
 

@@ -286,3 +286,31 @@ def test_workgroup_count_does_not_change_result(pk, wg):
     ref, _ = oracle.phipm(2e-3, A, b, tol=1e-9)
     assert st["workgroups"] == wg
     assert rel(u, ref) <= 1e-8
+
+
+FP32_CASES = [
+    # name, builder, p, t, tol
+    ("config1 lap2d-30 p1", None, 1, 1e-3, 1e-7),
+    ("lap3d-40 p3", lambda: W.laplace3d(40), 3, 1e-4, 1e-6),
+    ("convdiff-96 p0", lambda: W.convdiff2d(96, 40.0, 40.0), 0, 1e-2, 1e-7),
+    ("convdiff-96 p2", lambda: W.convdiff2d(96, 40.0, 40.0), 2, 1e-2, 1e-7),
+    ("reaction-128 p2", lambda: W.reaction2d(128, 5999), 2, 1e-3, 1e-6),
+]
+
+
+@pytest.mark.parametrize("name,build,p,t,tol", FP32_CASES)
+def test_fp32_basis_meets_gate(pk, name, build, p, t, tol):
+    """FP32 Krylov basis with FP64 Taylor part, exponential and control: within
+    10 tol (relative 2-norm) of the FP64 oracle."""
+    say("fp32 case", name)
+    if build is None:
+        pb = W.config1()
+        A, b = pb.A, pb.b
+    else:
+        A = build()
+        b = np.random.default_rng(9).standard_normal((A.shape[0], p + 1))
+    u, st = gpu_solve(pk, t, A, b, tol=tol, precision=pk.FP32_BASIS)
+    ref, _ = oracle.phipm(t, A, b, tol=tol)
+    say("  gpu fp32", st, "rel", rel(u, ref))
+    assert st["status"] == 0
+    assert rel(u, ref) <= 10 * tol
