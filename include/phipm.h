@@ -65,7 +65,11 @@ typedef struct {
   int32_t symm;          /* -1: detect exact symmetry (Sect. 3.5), 0: Arnoldi, 1: Lanczos */
   int32_t m_init;        /* initial Krylov dimension; default 10 (Algorithm 3) */
   int32_t m_max;         /* largest Krylov dimension; default 100, at most PHIPM_M_CAP */
-  int32_t precision;     /* PHIPM_FP64 or PHIPM_FP32_BASIS */
+  int32_t precision;     /* PHIPM_FP64, or PHIPM_FP32_BASIS: Krylov basis and CSR values
+                            stored in FP32 (products and sums accumulated in FP64; W, u,
+                            the small exponential and the control in FP64), with a
+                            per-solve fallback to FP64 when its rounding estimate would
+                            not fit the tolerance (see phipm_stats.fp64_fallback) */
   int32_t adapt_m;       /* 1: adapt m (phipm); 0: keep m fixed (the phip variant) */
   int32_t corrector;     /* 1: eq. phipapprox2 (default); 0: eq. phipapprox */
   double tau_fixed;      /* > 0: fixed substep, every attempt accepted (diagnostics) */
@@ -96,6 +100,12 @@ typedef struct {
                         basis column and vector counted once per pass that touches it */
   double phi_ratio_max;        /* FP32 basis: largest ||beta y||_2 / ||u_k||_2 of a step */
   int64_t precision_rejects;   /* FP32 basis: attempts rejected for basis rounding */
+  double fp32_error_estimate;  /* FP32 basis: accumulated absolute rounding estimate of the
+                                  FP32 phi-parts (of the FP32 run, if it fell back) */
+  int32_t fp64_fallback;       /* FP32 basis: 1 if the estimate exceeded 2 tol max(1, ||u||)
+                                  and the solve was repeated with the FP64 basis; the
+                                  counters then include both runs */
+  int32_t pad2_;
 } phipm_stats;
 
 void phipm_default_opts(phipm_opts* opts);
@@ -134,6 +144,106 @@ int phipm_expm(int N, const double* H, double* E, double* scratch, phipm_stream_
  * (lanczos = 1) flavour.  Returns the number of steps done in *m_done (host). */
 int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double* V, double* H,
                  void* workspace, size_t ws_bytes, int* m_done, phipm_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Many independent solves in one persistent launch.
+ *
+ * A plan binds `count` instances u_i = sum_k t_i^k phi_k(t_i A_i) b_{i,k},
+ * each exactly the problem of phipm() with the shared options, to one
+ * persistent kernel.  The grid (one workgroup per compute unit) is split into
+ * teams of power-of-two sizes; instances are grouped into team-size classes
+ * by cost and queued in descending cost; a team takes the next instance of
+ * its class's queue, then of the smaller classes' queues, until all are
+ * solved.  The team layout is chosen by an autotuner that times candidate
+ * layouts on the device with the plan's own instances (costs predicted from
+ * n_i, t_i, p_i and ||A_i||_inf, then measured).  The tuned launch is
+ * captured in a hipGraph that phipm_plan_execute() replays.
+ *
+ * Ownership: the plan allocates and owns its device memory (descriptors,
+ * one work buffer per team, per-instance statistics), released by
+ * phipm_plan_destroy().  It stores the caller's pointers: every A_i, b_i and
+ * u_i must stay allocated, with unchanged shapes, while the plan lives; the
+ * contents of b_i (and of A_i's values) may change between executions.
+ * Creating a plan with autotuning runs the whole batch several times (it
+ * writes u_i).  Executions of one plan must not overlap.
+ * ---------------------------------------------------------------------- */
+typedef struct phipm_plan phipm_plan;
+
+typedef struct {
+  int32_t autotune;  /* 1 (default): time candidate layouts at creation; 0: model layout */
+  int32_t graph;     /* 1 (default): capture the launch in a hipGraph */
+  int32_t max_team;  /* 0: library default (16); else largest team of the untuned layout,
+                        a power of two */
+  int32_t pad_;
+} phipm_plan_opts;
+
+typedef struct {
+  int32_t count;          /* instances */
+  int32_t workgroups;     /* grid size of the persistent kernel */
+  int32_t teams;          /* teams of the chosen layout */
+  int32_t classes;        /* team-size classes (at most 8 reported) */
+  int32_t class_size[8];  /* workgroups per team of each class, largest first */
+  int32_t class_teams[8]; /* teams of each class */
+  int32_t graph;          /* 1 if executions replay a captured hipGraph */
+  int32_t cooperative;    /* 1 if the persistent kernel is launched cooperatively */
+  int32_t candidates;     /* distinct layouts timed by the autotuner (0: not tuned) */
+  int32_t max_team;       /* largest team size allowed by the chosen layout */
+  double alpha;           /* cost threshold factor of the chosen layout */
+  double tuned_ms;        /* time of the chosen layout while tuning */
+  double default_ms;      /* time of the untuned layout while tuning */
+  uint64_t device_bytes;  /* device memory held by the plan */
+} phipm_plan_info;
+
+void phipm_default_plan_opts(phipm_plan_opts* popts);
+
+/* Create a plan for `count` >= 1 instances.  Host arrays of length count:
+ *   A   CSR descriptors (device pointers inside, as for phipm())
+ *   p   0 <= p_i <= PHIPM_P_MAX
+ *   t   finite end times
+ *   b   device pointers, n_i x (p_i+1) column-major float64
+ *   u   device pointers, n_i float64 outputs; no u_i may overlap another u_j
+ *       or its b_i
+ * opts applies to every instance (opts->workgroups > 0 caps the grid size).
+ * Work during creation (norms, tuning runs) is enqueued on `stream` and
+ * synchronised.  Returns PHIPM_OK and *plan, or an error (PHIPM_EINVAL,
+ * PHIPM_ENONFINITE for a non-finite t_i, PHIPM_ENOMEM, PHIPM_EHIP,
+ * PHIPM_EABORT). */
+int phipm_plan_create(int count, const phipm_csr* A, const int32_t* p, const double* t,
+                      const double* const* b, double* const* u, const phipm_opts* opts,
+                      const phipm_plan_opts* popts, phipm_stream_t stream, phipm_plan** plan);
+
+/* Solve all instances once (asynchronous on `stream`; must be called on the
+ * device the plan was created on). */
+int phipm_plan_execute(phipm_plan* plan, phipm_stream_t stream);
+
+/* Per-instance statistics of the last execution (host array of count
+ * entries; synchronises the stream of that execution).  Returns PHIPM_OK or
+ * the first instance's error. */
+int phipm_plan_stats(phipm_plan* plan, phipm_stats* stats);
+
+int phipm_plan_get_info(const phipm_plan* plan, phipm_plan_info* info);
+
+/* Synchronises the last execution's stream and frees the plan. */
+int phipm_plan_destroy(phipm_plan* plan);
+
+/* One-off convenience: create an untuned, uncaptured plan, execute it, fill
+ * stats (host, count entries, may be NULL), destroy it.  Synchronous; it
+ * allocates and frees the plan's device memory. */
+int phipm_batched(int count, const phipm_csr* A, const int32_t* p, const double* t,
+                  const double* const* b, double* const* u, const phipm_opts* opts,
+                  phipm_stats* stats, phipm_stream_t stream);
+
+/* Host-only, no device work: the team layout the planner derives from
+ * per-instance costs (cost[i] >= 0, any unit) for a grid of `workgroups`
+ * workgroups, teams of at most max_team (a power of two) and the threshold
+ * factor alpha > 0.  Outputs (host arrays): team_size[t], team_class[t] for
+ * t < *nteams (capacity workgroups); order (capacity count): instance ids,
+ * queue after queue; qbeg (capacity workgroups + 1): queue c is
+ * order[qbeg[c] .. qbeg[c+1]) for c < *nclasses.  Teams are listed in
+ * grid order (team t starts at the sum of the sizes before it). */
+int phipm_batch_layout(int count, const double* cost, int workgroups, int max_team,
+                       double alpha, int32_t* team_size, int32_t* team_class, int32_t* nteams,
+                       int32_t* order, int32_t* qbeg, int32_t* nclasses);
 
 const char* phipm_status_string(int status);
 

@@ -45,16 +45,41 @@ class Stats(C.Structure):
                 ("m_last", C.c_int32), ("status", C.c_int32), ("lanczos", C.c_int32),
                 ("workgroups", C.c_int32), ("anorm", C.c_double), ("setup_flags", C.c_int32),
                 ("pad_", C.c_int32), ("bytes", C.c_double), ("phi_ratio_max", C.c_double),
-                ("precision_rejects", C.c_int64)]
+                ("precision_rejects", C.c_int64), ("fp32_error_estimate", C.c_double),
+                ("fp64_fallback", C.c_int32), ("pad2_", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PlanOpts(C.Structure):
+    _fields_ = [("autotune", C.c_int32), ("graph", C.c_int32), ("max_team", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("count", C.c_int32), ("workgroups", C.c_int32), ("teams", C.c_int32),
+                ("classes", C.c_int32), ("class_size", C.c_int32 * 8),
+                ("class_teams", C.c_int32 * 8), ("graph", C.c_int32),
+                ("cooperative", C.c_int32), ("candidates", C.c_int32), ("max_team", C.c_int32),
+                ("alpha", C.c_double), ("tuned_ms", C.c_double), ("default_ms", C.c_double),
+                ("device_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        nc = self.classes
+        d["class_size"] = list(self.class_size)[:nc]
+        d["class_teams"] = list(self.class_teams)[:nc]
+        return d
+
+
 _lib = None
 
 EXPORTS = ["phipm_default_opts", "phipm_workspace_bytes", "phipm", "phipm_last_status",
-           "phipm_spmv", "phipm_expm", "phipm_krylov", "phipm_status_string"]
+           "phipm_spmv", "phipm_expm", "phipm_krylov", "phipm_status_string",
+           "phipm_default_plan_opts", "phipm_plan_create", "phipm_plan_execute",
+           "phipm_plan_stats", "phipm_plan_get_info", "phipm_plan_destroy", "phipm_batched",
+           "phipm_batch_layout"]
 
 
 def lib():
@@ -84,6 +109,26 @@ def lib():
         L.phipm_krylov.restype = C.c_int
         L.phipm_status_string.argtypes = [C.c_int]
         L.phipm_status_string.restype = C.c_char_p
+        L.phipm_default_plan_opts.argtypes = [C.POINTER(PlanOpts)]
+        L.phipm_default_plan_opts.restype = None
+        plan_args = [C.c_int, C.POINTER(CSR), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                     C.POINTER(vp), C.POINTER(vp), C.POINTER(Opts)]
+        L.phipm_plan_create.argtypes = plan_args + [C.POINTER(PlanOpts), vp, C.POINTER(vp)]
+        L.phipm_plan_create.restype = C.c_int
+        L.phipm_plan_execute.argtypes = [vp, vp]
+        L.phipm_plan_execute.restype = C.c_int
+        L.phipm_plan_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.phipm_plan_stats.restype = C.c_int
+        L.phipm_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
+        L.phipm_plan_get_info.restype = C.c_int
+        L.phipm_plan_destroy.argtypes = [vp]
+        L.phipm_plan_destroy.restype = C.c_int
+        L.phipm_batched.argtypes = plan_args + [C.POINTER(Stats), vp]
+        L.phipm_batched.restype = C.c_int
+        ip = C.POINTER(C.c_int32)
+        L.phipm_batch_layout.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int,
+                                         C.c_double, ip, ip, ip, ip, ip, ip]
+        L.phipm_batch_layout.restype = C.c_int
         _lib = L
     return _lib
 
@@ -222,3 +267,116 @@ def krylov(A: DeviceCSR, v, m: int, lanczos: bool, stream=None):
     if rc != OK:
         raise PhipmError(rc, "phipm_krylov")
     return V.view(m + 1, A.n).T, H.view(m + 1, m), done.value
+
+
+def default_plan_opts(**kw) -> PlanOpts:
+    o = PlanOpts()
+    lib().phipm_default_plan_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _batch_arrays(As, ps, ts, bs, us):
+    torch = _torch()
+    count = len(As)
+    if not (len(ps) == len(ts) == len(bs) == len(us) == count):
+        raise ValueError("instance lists differ in length")
+    for A, p, b, u in zip(As, ps, bs, us):
+        if b.dtype != torch.float64 or u.dtype != torch.float64:
+            raise TypeError("b and u must be float64")
+        if not b.is_contiguous() or tuple(b.shape) != (int(p) + 1, A.n) or u.numel() != A.n:
+            raise ValueError("b must be a contiguous (p+1, n) tensor and u an n-vector")
+    csr = (CSR * count)(*[A.c() for A in As])
+    pa = (C.c_int32 * count)(*[int(p) for p in ps])
+    ta = (C.c_double * count)(*[float(t) for t in ts])
+    ba = (C.c_void_p * count)(*[b.data_ptr() for b in bs])
+    ua = (C.c_void_p * count)(*[u.data_ptr() for u in us])
+    return csr, pa, ta, ba, ua
+
+
+class Plan:
+    """Many solves in one persistent launch (``phipm_plan_*``).
+
+    As: DeviceCSR list; ps: p_i; ts: t_i; bs: (p_i+1, n_i) float64 tensors;
+    us: n_i float64 output tensors.  The plan keeps references to every
+    tensor it was given, so they stay allocated while it lives."""
+
+    def __init__(self, As, ps, ts, bs, us, opts: Opts | None = None,
+                 plan_opts: PlanOpts | None = None, stream=None, **kw):
+        self._keep = (list(As), list(bs), list(us))
+        self.count = len(As)
+        self.opts = opts if opts is not None else default_opts(**kw)
+        self.plan_opts = plan_opts if plan_opts is not None else default_plan_opts()
+        arrs = _batch_arrays(As, ps, ts, bs, us)
+        self._arrs = arrs
+        h = C.c_void_p()
+        rc = lib().phipm_plan_create(self.count, *arrs, C.byref(self.opts),
+                                     C.byref(self.plan_opts), _stream_ptr(stream), C.byref(h))
+        if rc != OK:
+            raise PhipmError(rc, "phipm_plan_create")
+        self._h = h
+
+    def execute(self, stream=None):
+        rc = lib().phipm_plan_execute(self._h, _stream_ptr(stream))
+        if rc != OK:
+            raise PhipmError(rc, "phipm_plan_execute")
+
+    def stats(self, check: bool = True):
+        st = (Stats * self.count)()
+        rc = lib().phipm_plan_stats(self._h, st)
+        if check and rc != OK:
+            raise PhipmError(rc, "phipm_plan_stats")
+        return [s.as_dict() for s in st]
+
+    def info(self):
+        inf = PlanInfo()
+        rc = lib().phipm_plan_get_info(self._h, C.byref(inf))
+        if rc != OK:
+            raise PhipmError(rc, "phipm_plan_get_info")
+        return inf.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().phipm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batched(As, ps, ts, bs, us, opts: Opts | None = None, stream=None, **kw):
+    """One-off batched solve (``phipm_batched``); returns per-instance stats."""
+    o = opts if opts is not None else default_opts(**kw)
+    arrs = _batch_arrays(As, ps, ts, bs, us)
+    st = (Stats * len(As))()
+    rc = lib().phipm_batched(len(As), *arrs, C.byref(o), st, _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_batched")
+    return [s.as_dict() for s in st]
+
+
+def batch_layout(cost, workgroups: int, max_team: int, alpha: float):
+    """The planner's team layout for per-instance costs (host only, no GPU).
+    Returns dict(team_size, team_class, order, qbeg)."""
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    count = cost.size
+    ts = np.zeros(max(1, workgroups), dtype=np.int32)
+    tc = np.zeros_like(ts)
+    order = np.zeros(max(1, count), dtype=np.int32)
+    qbeg = np.zeros(max(1, workgroups) + 1, dtype=np.int32)
+    nt, nc = C.c_int32(), C.c_int32()
+    ip = C.POINTER(C.c_int32)
+    rc = lib().phipm_batch_layout(int(count), cost.ctypes.data_as(C.POINTER(C.c_double)),
+                                  int(workgroups), int(max_team), float(alpha),
+                                  ts.ctypes.data_as(ip), tc.ctypes.data_as(ip), C.byref(nt),
+                                  order.ctypes.data_as(ip), qbeg.ctypes.data_as(ip), C.byref(nc))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_batch_layout")
+    return {"team_size": ts[:nt.value].copy(), "team_class": tc[:nt.value].copy(),
+            "order": order[:count].copy(), "qbeg": qbeg[:nc.value + 1].copy()}

@@ -7,7 +7,7 @@
 #include <mutex>
 
 #include "../../include/phipm.h"
-#include "solver.hpp"
+#include "host_common.hpp"
 
 using namespace pkr;
 
@@ -27,8 +27,9 @@ __global__ __launch_bounds__(BLOCK) void k_solve(Problem P, Work<T> w, TeamCtl* 
                                                  double* partials, double* result,
                                                  unsigned long long spin) {
   __shared__ Shared sh;
-  Team tm{(int)blockIdx.x, (int)gridDim.x, ctl, partials, result, spin};
-  solve<T>(tm, P, w, sh);
+  const Team tm = make_team((int)blockIdx.x, (int)gridDim.x, &ctl->gen, &ctl->abort, partials,
+                            result, spin);
+  solve_mixed<T>(tm, P, w, sh);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_spmv(int n, const int* rp, const int* ci,
@@ -59,7 +60,8 @@ __global__ __launch_bounds__(BLOCK) void k_krylov(Problem P, Work<double> w, con
                                                   int* m_done, TeamCtl* ctl, double* partials,
                                                   double* result, unsigned long long spin) {
   __shared__ Shared sh;
-  Team tm{(int)blockIdx.x, (int)gridDim.x, ctl, partials, result, spin};
+  const Team tm = make_team((int)blockIdx.x, (int)gridDim.x, &ctl->gen, &ctl->abort, partials,
+                            result, spin);
   int rb, re;
   own_rows(tm, P.n, rb, re);
   double a = 0.0;
@@ -134,32 +136,20 @@ const DeviceInfo* device_info() {
   return &d;
 }
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-inline long long pad64(long long x) { return (x + 63) / 64 * 64; }
-
+// Work buffer of one solve followed by the team's control block, reduction
+// partials and result.
 struct Layout {
-  long long ldw, ldv;
-  size_t W, V, y0, y1, val32, H, ex, st, stats, ctl, part, res, total;
+  WorkLayout w;
+  size_t ctl, part, res, total;
 };
 
 Layout layout(int n, int nnz, int p, int m_cap, bool fp32, int gmax) {
   Layout L{};
-  const size_t tb = fp32 ? 4 : 8;
-  L.ldw = pad64(n);
-  L.ldv = pad64(n);
-  size_t off = 0;
+  L.w = work_layout(n, nnz, p, m_cap, fp32);
+  size_t off = L.w.total;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-  L.W = take(sizeof(double) * (size_t)L.ldw * (size_t)std::max(p, 1));
-  L.V = take(tb * (size_t)L.ldv * (size_t)(m_cap + 1));
-  L.y0 = take(tb * (size_t)L.ldv);
-  L.y1 = take(tb * (size_t)L.ldv);
-  L.val32 = take(fp32 ? sizeof(float) * (size_t)std::max(nnz, 1) : 0);
-  L.H = take(sizeof(double) * (M_CAP + 1) * M_CAP);
-  L.ex = take(sizeof(double) * 8 * (size_t)NMAX_EXPM * NMAX_EXPM);
-  L.st = take(sizeof(State));
-  L.stats = take(sizeof(Stats));
   L.ctl = take(sizeof(TeamCtl));
-  L.part = take(sizeof(double) * (size_t)KMAX * ((size_t)gmax + TEAM_NGROUPS));
+  L.part = take(sizeof(double) * team_partials(gmax));
   L.res = take(sizeof(double) * KMAX);
   L.total = off;
   return L;
@@ -174,17 +164,6 @@ int fail(int code) {
   t_last_host_status = code;
   t_last_stats = nullptr;
   return code;
-}
-
-bool opts_ok(const phipm_opts* o) {
-  return o && o->tol > 0.0 && std::isfinite(o->tol) && o->m_init >= 1 && o->m_max >= o->m_init &&
-         o->m_max <= PHIPM_M_CAP && (o->symm >= -1 && o->symm <= 1) &&
-         (o->precision == PHIPM_FP64 || o->precision == PHIPM_FP32_BASIS) && o->max_attempts >= 1 &&
-         o->workgroups >= 0 && std::isfinite(o->tau_fixed) && o->tau_fixed >= 0.0;
-}
-
-bool csr_ok(const phipm_csr* A) {
-  return A && A->n > 0 && A->nnz >= 0 && A->row_ptr && (A->nnz == 0 || (A->col_idx && A->val));
 }
 
 int choose_workgroups(const phipm_opts* o, int n, int gmax) {
@@ -244,13 +223,8 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   const Layout L = layout(A->n, A->nnz, p, m_cap, fp32, gmax);
   if (ws_bytes < L.total) return fail(PHIPM_ENOMEM);
   // u must not overlap b or the workspace
-  auto overlap = [](const void* a, size_t na, const void* c, size_t nc) {
-    const char* x = static_cast<const char*>(a);
-    const char* y = static_cast<const char*>(c);
-    return x < y + nc && y < x + na;
-  };
   const size_t ub = sizeof(double) * (size_t)A->n;
-  if (overlap(u, ub, b, ub * (size_t)(p + 1)) || overlap(u, ub, workspace, ws_bytes))
+  if (overlaps(u, ub, b, ub * (size_t)(p + 1)) || overlaps(u, ub, workspace, ws_bytes))
     return fail(PHIPM_EINVAL);
 
   char* ws = static_cast<char*>(workspace);
@@ -261,7 +235,7 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   P.rp = A->row_ptr;
   P.ci = A->col_idx;
   P.val = A->val;
-  P.val32 = reinterpret_cast<float*>(ws + L.val32);
+  P.val32 = reinterpret_cast<float*>(ws + L.w.val32);
   P.b = b;
   P.ldb = A->n;
   P.u = u;
@@ -279,7 +253,7 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   TeamCtl* ctl = reinterpret_cast<TeamCtl*>(ws + L.ctl);
   double* part = reinterpret_cast<double*>(ws + L.part);
   double* res = reinterpret_cast<double*>(ws + L.res);
-  Stats* dstats = reinterpret_cast<Stats*>(ws + L.stats);
+  Stats* dstats = reinterpret_cast<Stats*>(ws + L.w.stats);
   unsigned long long spin = d->spin_ticks;
   const int G = choose_workgroups(o, A->n, gmax);
 
@@ -287,18 +261,12 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   if (hipGetLastError() != hipSuccess) return fail(PHIPM_EHIP);
   hipError_t e;
   if (fp32) {
-    Work<float> w{reinterpret_cast<double*>(ws + L.W), L.ldw, reinterpret_cast<float*>(ws + L.V),
-                  L.ldv, reinterpret_cast<float*>(ws + L.y0), reinterpret_cast<float*>(ws + L.y1),
-                  reinterpret_cast<double*>(ws + L.H), reinterpret_cast<double*>(ws + L.ex),
-                  reinterpret_cast<State*>(ws + L.st), dstats};
+    Work<float> w = work_at<float>(ws, L.w);
     void* args[] = {&P, &w, &ctl, &part, &res, &spin};
     e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_solve<float>), dim3(G),
                                    dim3(BLOCK), args, 0, stream);
   } else {
-    Work<double> w{reinterpret_cast<double*>(ws + L.W), L.ldw, reinterpret_cast<double*>(ws + L.V),
-                   L.ldv, reinterpret_cast<double*>(ws + L.y0), reinterpret_cast<double*>(ws + L.y1),
-                   reinterpret_cast<double*>(ws + L.H), reinterpret_cast<double*>(ws + L.ex),
-                   reinterpret_cast<State*>(ws + L.st), dstats};
+    Work<double> w = work_at<double>(ws, L.w);
     void* args[] = {&P, &w, &ctl, &part, &res, &spin};
     e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_solve<double>), dim3(G),
                                    dim3(BLOCK), args, 0, stream);
@@ -315,22 +283,8 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
         hipMemcpyAsync(&hc, ctl, sizeof(TeamCtl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return fail(PHIPM_EHIP);
-    stats->steps = hs.steps;
-    stats->rejected = hs.rejected;
-    stats->matvecs = hs.matvecs;
-    stats->expms = hs.expms;
-    stats->t_reached = hs.t_reached;
-    stats->tau_last = hs.tau_last;
-    stats->m_last = hs.m_last;
-    stats->status = hc.abort ? PHIPM_EABORT : hs.status;
-    stats->lanczos = hs.lanczos;
+    copy_stats(hs, hc.abort ? PHIPM_EABORT : hs.status, stats);
     stats->workgroups = G;
-    stats->anorm = hs.anorm;
-    stats->setup_flags = hs.setup_flags;
-    stats->pad_ = 0;
-    stats->bytes = hs.bytes;
-    stats->phi_ratio_max = hs.rho_max;
-    stats->precision_rejects = hs.prec_rejects;
     return stats->status;
   }
   return PHIPM_OK;
@@ -385,13 +339,13 @@ int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double
   P.rp = A->row_ptr;
   P.ci = A->col_idx;
   P.val = A->val;
-  Work<double> w{nullptr, 0, V, A->n, reinterpret_cast<double*>(ws + L.y0),
-                 reinterpret_cast<double*>(ws + L.y1), reinterpret_cast<double*>(ws + L.H),
-                 nullptr, reinterpret_cast<State*>(ws + L.st), nullptr};
+  Work<double> w{nullptr, 0, V, A->n, reinterpret_cast<double*>(ws + L.w.y0),
+                 reinterpret_cast<double*>(ws + L.w.y1), reinterpret_cast<double*>(ws + L.w.H),
+                 nullptr, reinterpret_cast<State*>(ws + L.w.st), nullptr};
   TeamCtl* ctl = reinterpret_cast<TeamCtl*>(ws + L.ctl);
   double* part = reinterpret_cast<double*>(ws + L.part);
   double* res = reinterpret_cast<double*>(ws + L.res);
-  int* dm = reinterpret_cast<int*>(ws + L.stats);
+  int* dm = reinterpret_cast<int*>(ws + L.w.stats);
   unsigned long long spin = d->spin_ticks;
   phipm_opts o;
   phipm_default_opts(&o);

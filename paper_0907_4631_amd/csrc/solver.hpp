@@ -59,6 +59,8 @@ struct Stats {              // mirrors phipm_stats
   double bytes;
   double rho_max;
   long long prec_rejects;
+  double fp32_err;          // accumulated FP32 rounding estimate (absolute)
+  int fp64_fallback, pad2;
 };
 
 struct State {
@@ -68,6 +70,8 @@ struct State {
   double unorm;             // ||u_k||_2 of the current state
   double rho_max;           // largest ||beta y|| / ||u_k|| seen (FP32 basis)
   long long prec_rejects;   // attempts rejected for FP32 rounding
+  double fp32_err;          // sum over accepted steps of the FP32 rounding estimate
+  int need_fp64, pad3;      // the FP32 estimate ran over budget: solve again in FP64
   int setup_flags, pad0;
   double eps, omega, knorm;
   int m, m_cap, lanczos, zero_path;
@@ -244,6 +248,12 @@ __device__ __forceinline__ double krylov_step(const Team& tm, const Problem& P, 
   return hn;
 }
 
+enum { SOLVE_DONE = 0, SOLVE_ABORTED = -1, SOLVE_NEEDS_FP64 = 1 };
+
+// Share of the tolerance the FP32 rounding estimate may take (absolute,
+// against max(1, ||u_k||) after every accepted step).
+constexpr double FP32_BUDGET = 2.0;
+
 // Scalars the decision step needs (passed by value so that the out-of-line
 // call does not force the kernel arguments into private memory).
 struct DecideArgs {
@@ -355,6 +365,12 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
     // is rejected and tau shrunk (the Krylov basis does not depend on tau); on
     // acceptance the same bound caps the next tau.  With rho = O(1) FP32 is at
     // its floor and a smaller tau would not help.
+    double fp32_est = 0.0;  // absolute FP32 rounding estimate of this step's phi-part
+    if (a.fp32 && beta > 0.0) {
+      double ys = 0.0;
+      for (int k = 0; k < m_use; ++k) ys += st->yb[k] * st->yb[k];
+      fp32_est = EPS32 * sqrt(ys) * (knorm > 1.0 ? knorm : 1.0);
+    }
     if (a.fp32 && beta > 0.0 && !(a.tau_fixed > 0.0) && isfinite(omega)) {
       double ys = 0.0;
       for (int k = 0; k < m_use; ++k) ys += st->yb[k] * st->yb[k];
@@ -377,6 +393,15 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
         }
       }
     }
+    // FP32 basis: the absolute rounding estimate accumulated over the accepted
+    // steps must stay within FP32_BUDGET tol max(1, ||u_k||); an attempt that
+    // would take it over ends the FP32 solve (the caller repeats it in FP64).
+    if (a.fp32 && accept && !(a.tau_fixed > 0.0) &&
+        st->fp32_err + fp32_est > FP32_BUDGET * a.tol * fmax(1.0, st->unorm)) {
+      accept = 0;
+      st->need_fp64 = 1;
+      st->done = 1;
+    }
     st->eps = eps;
     st->omega = omega;
     st->knorm = knorm;
@@ -393,6 +418,7 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       if (t_end - tn <= 4.0 * 2.220446049250313e-16 * t_end) tn = t_end;
       st->t = tn;
       st->steps += 1;
+      st->fp32_err += fp32_est;
       st->tau_last = tau;
       st->m_last = m_use;
       st->mem = Alg4Mem{};
@@ -413,14 +439,21 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
   __syncthreads();
 }
 
+// Solve one problem.  Returns SOLVE_DONE, SOLVE_ABORTED (a team wait ran out
+// of time; the team must stop) or, for the FP32 basis only, SOLVE_NEEDS_FP64:
+// the accumulated rounding estimate of the FP32 phi-parts exceeds
+// FP32_BUDGET tol max(1, ||u_k||), so the result could miss the tolerance and
+// the caller solves the problem again with the FP64 basis.  The return value
+// is the same in every workgroup of the team.
 template <typename T>
-__device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Work<T>& w, Shared& sh) {
+__device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Work<T>& w, Shared& sh) {
   State* st = w.st;
   const int tid = threadIdx.x;
   const int n = P.n, p = P.p;
   int rb, re;
   own_rows(tm, n, rb, re);
   const bool fp32 = sizeof(T) == 4;
+  bool fallback = false;
 
   // ---------------------------------------------------------------- setup
   {
@@ -479,7 +512,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
       for (int r = rb + tid; r < re; r += BLOCK) bm[0] = nanmax(bm[0], fabs(bk[r]));
       block_reduce<1>(bm, RED_MAX, sh.blk + 4 + k);
     }
-    if (!team_sync(tm, sh.blk, 5 + p, RED_MAX, sh.red)) return;
+    if (!team_sync(tm, sh.blk, 5 + p, RED_MAX, sh.red)) return SOLVE_ABORTED;
     if (tm.rank == 0 && tid == 0) {
       const double* o = sh.red;
       st->status = ST_OK;
@@ -513,11 +546,13 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
       st->mem = Alg4Mem{};
       st->rho_max = 0.0;
       st->prec_rejects = 0;
+      st->fp32_err = 0.0;
+      st->need_fp64 = 0;
       st->unorm = 0.0;
       st->bytes = (check_sym ? 24.0 : 12.0) * P.nnz + 4.0 * (n + 1.0) + 8.0 * n * (p + 1.0) +
                   (fp32 ? 4.0 * P.nnz : 0.0);
     }
-    if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+    if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
   }
   const double sgn = st->sgn;
   const double t_end = st->t_end;
@@ -546,7 +581,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
     }
     if (tm.rank == 0 && tid == 0) st->bytes += 16.0 * n;
     block_reduce<1>(a1, RED_SUM, sh.blk);
-    if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+    if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
     if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
   }
 
@@ -581,9 +616,9 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
         if (j == p) {
           double a1[1] = {nrm};
           block_reduce<1>(a1, RED_SUM, sh.blk);
-          if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+          if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
         } else {
-          if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+          if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
         }
       }
       if (p == 0) {
@@ -592,7 +627,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
         for (int r = rb + tid; r < re; r += BLOCK) a += P.u[r] * P.u[r];
         double a1[1] = {a};
         block_reduce<1>(a1, RED_SUM, sh.blk);
-        if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+        if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
       }
       const double beta = sqrt(sh.red[0]);
       if (tm.rank == 0 && tid == 0) {
@@ -617,7 +652,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
             else
               h = krylov_step<T, T>(tm, P, w, valT, sgn, lanczos, have,
                                     (have - 1) & 1 ? w.y1 : w.y0, T(1.0 / hprev), rb, re, sh);
-            if (h < 0.0) return;  // aborted
+            if (h < 0.0) return SOLVE_ABORTED;  // aborted
             ++have;
             hprev = h;
             if (h <= st->bd_tol || have == n) broke = true;
@@ -636,7 +671,7 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
                         p, P.adapt_m, P.corrector, have, broke ? 1 : 0, fp32 ? 1 : 0};
           decide(da, st, w.H, w.ex, sh.dense);
         }
-        if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return;
+        if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
         if (!st->accept) {
           if (st->done) goto finish;  // attempt limit
           continue;
@@ -663,8 +698,15 @@ __device__ __forceinline__ void solve(const Team& tm, const Problem& P, const Wo
           st->bytes += 8.0 * n * (p > 0 ? p + 1.0 : 1.0) +
                        (use_v ? (mu + (use_corr ? 1.0 : 0.0)) * sizeof(T) * (double)n : 0.0);
         block_reduce<1>(un, RED_SUM, sh.blk);
-        if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
+        if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
         if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
+        // st->fp32_err was written before the decision's team_sync, so every
+        // workgroup sees the same value and takes the same branch
+        if (fp32 && !(P.tau_fixed > 0.0) &&
+            st->fp32_err > FP32_BUDGET * P.tol * fmax(1.0, sqrt(sh.red[0]))) {
+          fallback = true;
+          goto finish;
+        }
         break;
       }
     }
@@ -688,7 +730,50 @@ finish:
     o->bytes = st->bytes;
     o->rho_max = st->rho_max;
     o->prec_rejects = st->prec_rejects;
+    o->fp32_err = st->fp32_err;
+    o->fp64_fallback = 0;
   }
+  return (fallback || st->need_fp64) ? SOLVE_NEEDS_FP64 : SOLVE_DONE;
+}
+
+// solve() with the FP32 basis, and again with the FP64 basis if the FP32
+// rounding estimate ran over its budget (the work buffer is sized for FP64
+// vectors in both cases).  The statistics of a fallback count the work of
+// both runs and carry the FP32 run's estimate.
+template <typename T>
+__device__ __forceinline__ int solve_mixed(const Team& tm, const Problem& P, const Work<T>& w,
+                                           Shared& sh) {
+  int r = solve<T>(tm, P, w, sh);
+  if constexpr (sizeof(T) == 4) {
+    if (r == SOLVE_NEEDS_FP64) {
+      __shared__ long long s_carry[4];
+      __shared__ double s_carry_d[2];
+      if (tm.rank == 0 && threadIdx.x == 0) {
+        const Stats* o = w.stats;
+        s_carry[0] = o->steps;
+        s_carry[1] = o->rejected;
+        s_carry[2] = o->matvecs;
+        s_carry[3] = o->expms;
+        s_carry_d[0] = o->bytes;
+        s_carry_d[1] = o->fp32_err;
+      }
+      Work<double> wd{w.W, w.ldw, reinterpret_cast<double*>(w.V), w.ldv,
+                      reinterpret_cast<double*>(w.y0), reinterpret_cast<double*>(w.y1), w.H,
+                      w.ex, w.st, w.stats};
+      r = solve<double>(tm, P, wd, sh);
+      if (r == SOLVE_DONE && tm.rank == 0 && threadIdx.x == 0) {
+        Stats* o = w.stats;
+        o->steps += s_carry[0];
+        o->rejected += s_carry[1];
+        o->matvecs += s_carry[2];
+        o->expms += s_carry[3];
+        o->bytes += s_carry_d[0];
+        o->fp32_err = s_carry_d[1];
+        o->fp64_fallback = 1;
+      }
+    }
+  }
+  return r;
 }
 
 }  // namespace pkr

@@ -38,11 +38,42 @@ struct TeamCtl {
 struct Team {
   int rank;            // this workgroup's index in the team
   int size;            // workgroups in the team
-  TeamCtl* ctl;
+  unsigned* gen;       // the team's generation word
+  unsigned* abort;     // abort flag shared by every team of the launch
+  unsigned* garr;      // group leaders' epochs, FLAG_STRIDE apart
+  unsigned* arr;       // members' epochs, FLAG_STRIDE apart
   double* partials;    // [KMAX][size] per-workgroup values, then [KMAX][groups] group sums
   double* result;      // [KMAX]
   uint64_t spin_ticks; // wall-clock budget of one wait
 };
+
+// Flag words a team of `size` workgroups needs (generation line, group lines,
+// member lines).
+__host__ __device__ inline size_t team_flag_words(int size) {
+  return (size_t)FLAG_STRIDE * (1 + (size + TEAM_GROUP - 1) / TEAM_GROUP + size);
+}
+
+// A team whose flags live in `flags` (team_flag_words(size) zeroed words).
+__device__ __forceinline__ Team make_team(int rank, int size, unsigned* flags, unsigned* abort,
+                                          double* partials, double* result, uint64_t spin) {
+  const int ngroups = (size + TEAM_GROUP - 1) / TEAM_GROUP;
+  Team tm;
+  tm.rank = rank;
+  tm.size = size;
+  tm.gen = flags;
+  tm.abort = abort;
+  tm.garr = flags + FLAG_STRIDE;
+  tm.arr = flags + FLAG_STRIDE * (1 + ngroups);
+  tm.partials = partials;
+  tm.result = result;
+  tm.spin_ticks = spin;
+  return tm;
+}
+
+// Partials a team needs (doubles).
+__host__ __device__ inline size_t team_partials(int size) {
+  return (size_t)KMAX * (size + (size + TEAM_GROUP - 1) / TEAM_GROUP);
+}
 
 enum RedOp { RED_SUM = 0, RED_MAX = 1 };
 
@@ -155,9 +186,9 @@ __device__ __forceinline__ int wait_flags(const Team& tm, unsigned* flags, int c
     all = __all((int)(f - e) >= 0);
     if (!all) {
       __builtin_amdgcn_s_sleep(1);
-      if (ld_relaxed(&tm.ctl->abort)) ok = 0;
+      if (ld_relaxed(tm.abort)) ok = 0;
       else if (wall_clock64() - t0 > tm.spin_ticks) {
-        st_relaxed(&tm.ctl->abort, 1u);
+        st_relaxed(tm.abort, 1u);
         ok = 0;
       }
     }
@@ -192,17 +223,17 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
   for (int k = tid; k < K; k += BLOCK) tm.partials[(size_t)k * tm.size + tm.rank] = blk[k];
   __syncthreads();
   if (tid == 0) {
-    const unsigned e = ld_relaxed(&tm.ctl->gen) + 1u;
+    const unsigned e = ld_relaxed(tm.gen) + 1u;
     s_epoch = e;
     s_ok = 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    st_relaxed(&tm.ctl->arr[tm.rank][0], e);
+    st_relaxed(tm.arr + (size_t)tm.rank * FLAG_STRIDE, e);
   }
   __syncthreads();
   const unsigned e = s_epoch;
   if (leader) {
     if (tid < WAVE) {
-      const int ok = wait_flags(tm, &tm.ctl->arr[g0][0], gsz, e);
+      const int ok = wait_flags(tm, tm.arr + (size_t)g0 * FLAG_STRIDE, gsz, e);
       if (tid == 0) {
         s_ok = ok;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -214,11 +245,11 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
     __syncthreads();
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      st_relaxed(&tm.ctl->garr[grp][0], e);
+      st_relaxed(tm.garr + (size_t)grp * FLAG_STRIDE, e);
     }
     if (tm.rank == 0) {
       if (tid < WAVE) {
-        const int ok = wait_flags(tm, &tm.ctl->garr[0][0], ngroups, e);
+        const int ok = wait_flags(tm, tm.garr, ngroups, e);
         if (tid == 0) {
           s_ok = ok;
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -230,18 +261,18 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
       __syncthreads();
       if (tid == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        st_relaxed(&tm.ctl->gen, e);
+        st_relaxed(tm.gen, e);
       }
     }
   }
   if (tm.rank != 0 && tid == 0) {
     const uint64_t t0 = wall_clock64();
     int ok = 1;
-    while (ok && (int)(ld_relaxed(&tm.ctl->gen) - e) < 0) {
+    while (ok && (int)(ld_relaxed(tm.gen) - e) < 0) {
       __builtin_amdgcn_s_sleep(1);
-      if (ld_relaxed(&tm.ctl->abort)) ok = 0;
+      if (ld_relaxed(tm.abort)) ok = 0;
       else if (wall_clock64() - t0 > tm.spin_ticks) {
-        st_relaxed(&tm.ctl->abort, 1u);
+        st_relaxed(tm.abort, 1u);
         ok = 0;
       }
     }
