@@ -63,6 +63,12 @@ class Alg4State(C.Structure):
                 ("m_old", C.c_int32), ("pad_", C.c_int32)]
 
 
+class LabelCosts(C.Structure):
+    _fields_ = [("sync_s", C.c_double), ("sync1_s", C.c_double), ("bw_bytes_per_s", C.c_double),
+                ("wg_bytes_per_s", C.c_double), ("workgroups", C.c_int32), ("pad_", C.c_int32),
+                ("expm_s", C.c_double * 138)]
+
+
 _lib = None
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -107,6 +113,30 @@ def lib():
                                   C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, _dp,
                                   C.POINTER(C.c_double)]
         L.oracle_step.restype = C.c_int
+        L.oracle_gelu.argtypes = [C.c_double]
+        L.oracle_gelu.restype = C.c_double
+        L.oracle_gelu_grad.argtypes = [C.c_double]
+        L.oracle_gelu_grad.restype = C.c_double
+        L.oracle_mlp_params.argtypes = []
+        L.oracle_mlp_params.restype = C.c_int
+        L.oracle_mlp_forward.argtypes = [_dp, _dp, C.c_int, _dp]
+        L.oracle_mlp_forward.restype = None
+        L.oracle_mlp_loss_grad.argtypes = [_dp, _dp, _dp, C.c_int, C.c_void_p]
+        L.oracle_mlp_loss_grad.restype = C.c_double
+        L.oracle_adam_step.argtypes = [_dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_longlong]
+        L.oracle_adam_step.restype = None
+        L.oracle_step_omega.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, C.POINTER(C.c_double)]
+        L.oracle_step_omega.restype = C.c_double
+        L.oracle_step_time.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                       C.POINTER(LabelCosts)]
+        L.oracle_step_time.restype = C.c_double
+        L.oracle_label_step.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                        C.c_double, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, C.c_double,
+                                        C.POINTER(LabelCosts), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int)]
+        L.oracle_label_step.restype = None
         _lib = L
     return _lib
 
@@ -234,3 +264,71 @@ def step(A, b, t_k, u_k, tau, m, lanczos, reorth=1, corrector=1):
                       np.ascontiguousarray(u_k, dtype=np.float64), float(tau), int(m),
                       int(lanczos), int(reorth), int(corrector), out, C.byref(eps))
     return out, eps.value
+
+
+# ------------------------------------------------------------ proposer references
+
+def gelu(z):
+    return lib().oracle_gelu(float(z))
+
+
+def gelu_grad(z):
+    return lib().oracle_gelu_grad(float(z))
+
+
+def mlp_forward(P, X):
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    X = np.ascontiguousarray(np.atleast_2d(X), dtype=np.float64)
+    Y = np.empty((X.shape[0], 2))
+    lib().oracle_mlp_forward(P, X, X.shape[0], Y)
+    return Y
+
+
+def mlp_loss_grad(P, X, T, want_grad=True):
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    g = np.zeros(P.size) if want_grad else None
+    L = lib().oracle_mlp_loss_grad(P, X, T, X.shape[0],
+                                   g.ctypes.data_as(C.c_void_p) if want_grad else None)
+    return (L, g) if want_grad else L
+
+
+def adam_step(P, m, v, g, lr, t):
+    P, m, v = (np.array(a, dtype=np.float64) for a in (P, m, v))
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().oracle_adam_step(P, m, v, g, P.size, float(lr), int(t))
+    return P, m, v
+
+
+def step_omega(H, mm, p, beta, tau, t_end, tol):
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    kn = C.c_double()
+    w = lib().oracle_step_omega(H, H.shape[1], int(mm), int(p), float(beta), float(tau),
+                                float(t_end), float(tol), C.byref(kn))
+    return w, kn.value
+
+
+def label_costs(sync_s, sync1_s, bw, wg_bw, workgroups, expm_s):
+    c = LabelCosts()
+    c.sync_s, c.sync1_s, c.bw_bytes_per_s, c.wg_bytes_per_s = sync_s, sync1_s, bw, wg_bw
+    c.workgroups = int(workgroups)
+    for i, v in enumerate(expm_s):
+        c.expm_s[i] = float(v)
+    return c
+
+
+def step_time(mm, p, lanczos, n, nnz, costs):
+    return lib().oracle_step_time(int(mm), int(p), int(lanczos), float(n), float(nnz),
+                                  C.byref(costs))
+
+
+def label_step(H, m_use, m_have, p, lanczos, n, nnz, t, tau, beta, t_end, tol, costs=None):
+    """H: (m_have+1) x ldh row-major array; costs: LabelCosts or None (eq. 4)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    ts, ms = C.c_double(), C.c_int()
+    lib().oracle_label_step(H, H.shape[1], int(m_use), int(m_have), int(p), int(lanczos),
+                            float(n), float(nnz), float(t), float(tau), float(beta),
+                            float(t_end), float(tol), C.byref(costs) if costs else None,
+                            C.byref(ts), C.byref(ms))
+    return ts.value, ms.value

@@ -21,6 +21,9 @@
  *                        block matrix (Lemma 2.1 / eq. phide), diagonal A,
  *                        A = 0, eigenvector decay, stepping and resume
  *                        identities (eq. steppre), linearity, forward-back.
+ *   oracle_gelu, oracle_mlp_*, oracle_adam_step, oracle_label_step
+ *                        pinned: GELU closed forms, finite differences,
+ *                        Adam's first step, brute-force omega scans.
  *   oracle_tau0, oracle_cost_*, oracle_alg4
  *                        pinned by properties (fixed points at omega=gamma,
  *                        recovery of a known order / decay rate).  The
@@ -123,6 +126,33 @@ int    oracle_step(int n, const int32_t* rp, const int32_t* ci, const double* va
                    int p, const double* b, double t_k, const double* u_k,
                    double tau, int m, int lanczos, int reorth, int corrector,
                    double* u_next, double* eps);
+
+/* Learned (tau, m) proposer references (FP64).  Parameters: 5122 doubles,
+ * W1[64][12] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]; X rows x 12, T/Y
+ * rows x 2, row-major.  Pinned: GELU closed forms and limits, the gradient
+ * against central finite differences of the loss, Adam's first-step closed
+ * form, the label against a brute-force scan of omega. */
+double oracle_gelu(double z);
+double oracle_gelu_grad(double z);
+int    oracle_mlp_params(void);
+void   oracle_mlp_forward(const double* P, const double* X, int rows, double* Y);
+double oracle_mlp_loss_grad(const double* P, const double* X, const double* T, int rows,
+                            double* grad);
+void   oracle_adam_step(double* P, double* m, double* v, const double* g, int n, double lr,
+                        long long t);
+double oracle_step_omega(const double* H, int ldh, int mm, int p, double beta, double tau,
+                         double t_end, double tol, double* knorm);
+typedef struct {
+  double  sync_s, sync1_s, bw_bytes_per_s, wg_bytes_per_s;
+  int32_t workgroups, pad_;
+  double  expm_s[128 + 8 + 2];
+} oracle_label_costs;
+double oracle_step_time(int mm, int p, int lanczos, double n, double nnz,
+                        const oracle_label_costs* c);
+void   oracle_label_step(const double* H, int ldh, int m_use, int m_have, int p, int lanczos,
+                         double n, double nnz, double t, double tau, double beta, double t_end,
+                         double tol, const oracle_label_costs* costs, double* tau_star,
+                         int* m_star);
 
 #ifdef __cplusplus
 }

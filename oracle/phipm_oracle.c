@@ -674,3 +674,203 @@ done:
   free(b);
   return status;
 }
+
+/* ------------------------------------------------------------------------
+ * Learned (tau, m) proposer: plain FP64 references of the network, its loss
+ * gradient, one Adam update (Kingma & Ba) and the hindsight label of a
+ * recorded step.  Parameter order: W1[64][12] b1[64] W2[64][64] b2[64]
+ * W3[2][64] b3[2].
+ * ---------------------------------------------------------------------- */
+
+enum { MI = 12, MH = 64, MO = 2 };
+enum { PW1 = 0, PB1 = PW1 + MH * MI, PW2 = PB1 + MH, PB2 = PW2 + MH * MH, PW3 = PB2 + MH,
+       PB3 = PW3 + MO * MH, PN = PB3 + MO };
+
+/* GELU in its tanh form (Hendrycks & Gimpel): 0.5 z (1 + tanh(c (z + a z^3))). */
+double oracle_gelu(double z) {
+  const double c = sqrt(2.0 / M_PI), a = 0.044715;
+  return 0.5 * z * (1.0 + tanh(c * (z + a * z * z * z)));
+}
+
+double oracle_gelu_grad(double z) {
+  const double c = sqrt(2.0 / M_PI), a = 0.044715;
+  const double th = tanh(c * (z + a * z * z * z));
+  return 0.5 * (1.0 + th) + 0.5 * z * (1.0 - th * th) * c * (1.0 + 3.0 * a * z * z);
+}
+
+int oracle_mlp_params(void) { return PN; }
+
+/* Forward pass of one row; z1, a1, z2, a2 (64 each) may be NULL. */
+static void mlp_row(const double* P, const double* x, double* y, double* z1, double* a1,
+                    double* z2, double* a2) {
+  double Z1[MH], A1[MH], Z2[MH], A2[MH];
+  for (int j = 0; j < MH; ++j) {
+    double s = P[PB1 + j];
+    for (int i = 0; i < MI; ++i) s += P[PW1 + j * MI + i] * x[i];
+    Z1[j] = s;
+    A1[j] = oracle_gelu(s);
+  }
+  for (int j = 0; j < MH; ++j) {
+    double s = P[PB2 + j];
+    for (int k = 0; k < MH; ++k) s += P[PW2 + j * MH + k] * A1[k];
+    Z2[j] = s;
+    A2[j] = oracle_gelu(s);
+  }
+  for (int o = 0; o < MO; ++o) {
+    double s = P[PB3 + o];
+    for (int j = 0; j < MH; ++j) s += P[PW3 + o * MH + j] * A2[j];
+    y[o] = s;
+  }
+  if (z1) memcpy(z1, Z1, sizeof Z1);
+  if (a1) memcpy(a1, A1, sizeof A1);
+  if (z2) memcpy(z2, Z2, sizeof Z2);
+  if (a2) memcpy(a2, A2, sizeof A2);
+}
+
+void oracle_mlp_forward(const double* P, const double* X, int rows, double* Y) {
+  for (int r = 0; r < rows; ++r) mlp_row(P, X + (size_t)r * MI, Y + (size_t)r * MO, 0, 0, 0, 0);
+}
+
+/* L = 1/(2 rows) sum_r sum_o (y_ro - t_ro)^2 and dL/dP by backpropagation
+ * (chain rule layer by layer).  Returns L. */
+double oracle_mlp_loss_grad(const double* P, const double* X, const double* T, int rows,
+                            double* grad) {
+  double L = 0.0;
+  if (grad) memset(grad, 0, sizeof(double) * PN);
+  for (int r = 0; r < rows; ++r) {
+    double y[MO], z1[MH], a1[MH], z2[MH], a2[MH];
+    const double* x = X + (size_t)r * MI;
+    mlp_row(P, x, y, z1, a1, z2, a2);
+    double dy[MO];
+    for (int o = 0; o < MO; ++o) {
+      const double e = y[o] - T[(size_t)r * MO + o];
+      L += e * e;
+      dy[o] = e / rows;
+    }
+    if (!grad) continue;
+    double dz2[MH], dz1[MH];
+    for (int o = 0; o < MO; ++o) {
+      grad[PB3 + o] += dy[o];
+      for (int j = 0; j < MH; ++j) grad[PW3 + o * MH + j] += dy[o] * a2[j];
+    }
+    for (int j = 0; j < MH; ++j) {
+      double d = 0.0;
+      for (int o = 0; o < MO; ++o) d += dy[o] * P[PW3 + o * MH + j];
+      dz2[j] = d * oracle_gelu_grad(z2[j]);
+    }
+    for (int j = 0; j < MH; ++j) {
+      grad[PB2 + j] += dz2[j];
+      for (int k = 0; k < MH; ++k) grad[PW2 + j * MH + k] += dz2[j] * a1[k];
+    }
+    for (int k = 0; k < MH; ++k) {
+      double d = 0.0;
+      for (int j = 0; j < MH; ++j) d += dz2[j] * P[PW2 + j * MH + k];
+      dz1[k] = d * oracle_gelu_grad(z1[k]);
+    }
+    for (int j = 0; j < MH; ++j) {
+      grad[PB1 + j] += dz1[j];
+      for (int i = 0; i < MI; ++i) grad[PW1 + j * MI + i] += dz1[j] * x[i];
+    }
+  }
+  return L / (2.0 * rows);
+}
+
+/* One Adam update with step number t (1-based): beta1 0.9, beta2 0.999, eps 1e-8. */
+void oracle_adam_step(double* P, double* m, double* v, const double* g, int n, double lr,
+                      long long t) {
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  for (int i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    const double mh = m[i] / (1.0 - pow(b1, (double)t));
+    const double vh = v[i] / (1.0 - pow(b2, (double)t));
+    P[i] -= lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+/* omega(tau) of eq. taunew for the first mm columns of a step's H (row-major,
+ * row stride ldh), with beta = ||w_p||; *knorm = ||tau K||_1. */
+double oracle_step_omega(const double* H, int ldh, int mm, int p, double beta, double tau,
+                         double t_end, double tol, double* knorm) {
+  double* y = (double*)malloc(sizeof(double) * (size_t)mm);
+  double c;
+  double nrm = augmented_expm(H, ldh, mm, p, tau, y, &c);
+  free(y);
+  if (knorm) *knorm = nrm;
+  const double eps = beta * fabs(H[(size_t)mm * ldh + (mm - 1)]) * fabs(c);
+  return t_end * eps / (tau * tol);
+}
+
+/* Time of a step of Krylov dimension mm under the device time model of the
+ * library (barriers, streamed algorithmic bytes, small exponential). */
+double oracle_step_time(int mm, int p, int lanczos, double n, double nnz,
+                        const oracle_label_costs* c) {
+  const double s = 8.0;
+  const double S = (s + 4.0) * nnz + 4.0 * (n + 1.0) + 2.0 * s * n;
+  double bytes = p * S;
+  for (int j = 1; j <= p; ++j) bytes += s * n * (p - j + 1);
+  for (int j = 0; j < mm; ++j) {
+    const double K = lanczos ? fmin(j + 1.0, 2.0) : j + 1.0;
+    bytes += S + (4.0 * K + 8.0) * s * n;
+  }
+  bytes += 2.0 * s * n + s * n * fmax(p + 1.0, 1.0) + (mm + 1.0) * s * n;
+  double G = fmin(fmax(ceil(n / 1024.0), 1.0), (double)c->workgroups);
+  const double bw = fmin(c->bw_bytes_per_s, G * c->wg_bytes_per_s);
+  const double sync = G > 1.0 ? c->sync_s : c->sync1_s;
+  const double syncs = 3.0 * mm + fmax((double)p, 1.0) + 2.0;
+  return syncs * sync + bytes / bw + c->expm_s[mm + p + 1];
+}
+
+/* Hindsight label of an accepted step (reading of the training target): over
+ * the candidate dimensions m' in {1, ..., 16, 20, 24, ...} up to m_have (and
+ * m_have itself), take tau*(m') = sup{tau in [tau_used/4096, t_end - t] :
+ * omega(tau, m') <= gamma} (bisection on log tau to full double precision;
+ * the whole interval if omega <= gamma at its top, its bottom if omega >
+ * gamma there; t_end - t if h_{m'+1,m'} = 0), and return the pair of least
+ * cost per unit time: C1(m') / tau*(m') (eq. 4 with M from ||tau* K||_1)
+ * without a time model, the modelled step time / tau*(m') with one. */
+void oracle_label_step(const double* H, int ldh, int m_use, int m_have, int p, int lanczos,
+                       double n, double nnz, double t, double tau, double beta, double t_end,
+                       double tol, const oracle_label_costs* costs, double* tau_star,
+                       int* m_star) {
+  const double gamma = 0.8;
+  const double rem = t_end - t;
+  double best = INFINITY;
+  *tau_star = tau;
+  *m_star = m_use;
+  for (int mm = 1; mm <= m_have;) {
+    double ts, kn;
+    if (H[(size_t)mm * ldh + (mm - 1)] == 0.0) {
+      ts = rem;
+      oracle_step_omega(H, ldh, mm, p, beta, ts, t_end, tol, &kn);
+    } else {
+      double a = tau / 4096.0, b = rem;
+      if (a > b) a = b;
+      if (oracle_step_omega(H, ldh, mm, p, beta, b, t_end, tol, &kn) <= gamma) {
+        ts = b;
+      } else if (oracle_step_omega(H, ldh, mm, p, beta, a, t_end, tol, &kn) > gamma) {
+        ts = a;
+      } else {
+        for (int it = 0; it < 200 && b > a * (1.0 + 4.0 * DBL_EPSILON); ++it) {
+          const double mid = sqrt(a * b);
+          if (mid <= a || mid >= b) break;
+          if (oracle_step_omega(H, ldh, mm, p, beta, mid, t_end, tol, &kn) <= gamma) a = mid;
+          else b = mid;
+        }
+        ts = a;
+        oracle_step_omega(H, ldh, mm, p, beta, ts, t_end, tol, &kn);
+      }
+    }
+    const double work = costs ? oracle_step_time(mm, p, lanczos, n, nnz, costs)
+                              : oracle_cost_C1(lanczos, mm, p, nnz, n, oracle_cost_M(kn));
+    const double cost = work / ts;
+    if (cost < best) {
+      best = cost;
+      *tau_star = ts;
+      *m_star = mm;
+    }
+    int nx = mm < 16 ? mm + 1 : (mm / 4 + 1) * 4;
+    if (nx > m_have && mm < m_have) nx = m_have;
+    mm = nx;
+  }
+}
