@@ -49,6 +49,14 @@ WORKLOADS = {
                       "tol=1e-6, Lanczos", "fp64"),
     "laplace2d-30": ("config1", "2D 5-point Laplacian 30x30 (n=900), p=1, t=1e-3, tol=1e-7, "
                      "Lanczos, FP64", "fp64"),
+    "reaction2d-1024-calls": ("config5", "2D diffusion-reaction Jacobian 1024x1024 "
+                              "(Laplacian + diag(1 - 3 u^2), n=1048576), p=2, t=1e-3, tol=1e-6, "
+                              "successive calls with new b; learned (tau, m) proposer vs plain "
+                              "step control (cold and warm start)", "fp64"),
+    "convdiff2d-batch256": ("config4", "256 independent 2D upwind convection-diffusion solves "
+                            "(N_i in 32..256, Peclet in 0..100, p_i in 0..3, t_i in 1e-4..1e-1, "
+                            "tol=1e-7) in one persistent autotuned launch replayed from a hipGraph",
+                            "fp64"),
 }
 
 
@@ -78,6 +86,173 @@ def cpu_baseline(pb, gpu_attempts, budget_s=20.0):
                       f"({dt:.1f} s), scaled by attempt count"}
 
 
+def cpu_baseline_batch(probs, gpu_stats, budget_s=20.0, seed=7):
+    """The oracle on the host cores, timed on a seeded random sample of the
+    batch's instances (about budget_s of CPU work) and scaled to the whole
+    batch by rows x products (the GPU run's product counts)."""
+    import oracle
+    oracle.build(force=False)
+    order = np.random.default_rng(seed).permutation(len(probs))
+    spent, work_done, done = 0.0, 0.0, 0
+    for i in order:
+        pb = probs[i]
+        w = pb.n * max(1, gpu_stats[i]["matvecs"])
+        t0 = time.perf_counter()
+        oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol)
+        spent += time.perf_counter() - t0
+        work_done += w
+        done += 1
+        if spent > budget_s:
+            break
+    total = sum(pb.n * max(1, s["matvecs"]) for pb, s in zip(probs, gpu_stats))
+    per_batch = spent * total / work_done
+    return {"value": len(probs) / per_batch, "unit": "solves/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{done} randomly chosen of the {len(probs)} instances ({spent:.1f} s), "
+                      f"scaled to the batch by rows x products"}
+
+
+def run_calls(args):
+    """Successive calls on one operator with new right-hand sides: the
+    learned proposer (the timed variant) beside the plain step control cold
+    and warm-started, and the FP32 basis."""
+    import torch
+    import paper_0907_4631_amd as pk
+    from paper_0907_4631_amd import proposer as PR
+    import workloads as W
+    A = W.config5_matrix()
+    n = A.shape[0]
+    t, tol, calls = 1e-3, 1e-6, args.steps
+    Ad = pk.DeviceCSR(A)
+    bs = [torch.as_tensor(np.ascontiguousarray(W.config5_b(c, n).T), device="cuda")
+          for c in range(calls)]
+    weights = PR.load()
+    variants = [("learned", pk.FP64, True, False), ("plain-cold", pk.FP64, False, False),
+                ("plain-warm", pk.FP64, False, True), ("learned-fp32-basis", pk.FP32_BASIS, True,
+                                                        False)]
+    res, outs = {}, {}
+    for name, prec, learned, warm in variants:
+        s = pk.Solver(Ad, 2, tol=tol, precision=prec)
+        hist = torch.zeros(4, dtype=torch.float64, device="cuda")
+        if warm:
+            s.opts.history = hist.data_ptr()
+        if learned:
+            s.opts.proposer = weights.data_ptr()
+        us = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(calls)]
+        for w in range(max(1, args.warmup)):
+            s(t, bs[w % calls], us[0], stats=False)
+        hist.zero_()
+        torch.cuda.synchronize()
+        tot = {"steps": 0, "rejected": 0, "matvecs": 0, "fp64_fallbacks": 0}
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for c in range(calls):
+            s(t, bs[c], us[c], stats=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / calls
+        if pk.lib().phipm_last_status() != 0:
+            raise pk.PhipmError(pk.lib().phipm_last_status(), name)
+        for c in range(calls):   # statistics from an untimed repeat of every call
+            st = s(t, bs[c], us[c])
+            for k in ("steps", "rejected", "matvecs"):
+                tot[k] += st[k]
+            tot["fp64_fallbacks"] += st["fp64_fallback"]
+        outs[name] = [u.cpu().numpy() for u in us]
+        res[name] = {"ms_per_call": ms, "calls_per_s": 1e3 / ms, **tot}
+    ref = outs["plain-cold"]
+    for name in res:
+        res[name]["max_diff_vs_plain_cold"] = max(
+            float(np.linalg.norm(a - b) / max(1.0, np.linalg.norm(b)))
+            for a, b in zip(outs[name], ref))
+    ms = res["learned"]["ms_per_call"]
+    line = {
+        "metric": "phipm solves/s (adaptive Krylov phi-function solve to t_end) and HBM GB/s",
+        "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": calls,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["reaction2d-1024-calls"][1], "n": n, "nnz": int(A.nnz),
+                   "calls": calls, "variants": res},
+    }
+    if not args.no_cpu:
+        class _P:
+            pass
+        pb = _P()
+        pb.A, pb.b, pb.t, pb.tol = A, W.config5_b(0, n), t, tol
+        line["cpu_baseline"] = cpu_baseline(pb, max(1, res["plain-cold"]["steps"] +
+                                                     res["plain-cold"]["rejected"]) // calls)
+        line["cpu_baseline"]["sample"] += " (plain step control, one call)"
+    print(json.dumps(line), flush=True)
+
+
+def run_batch(args):
+    import torch
+    import paper_0907_4631_amd as pk
+    import workloads as W
+    specs = W.config4_specs()
+    probs = [W.config4_problem(s) for s in specs]
+    As = [pk.DeviceCSR(pb.A) for pb in probs]
+    bs = [torch.as_tensor(np.ascontiguousarray(pb.b.T), device="cuda") for pb in probs]
+    us = [torch.empty(pb.n, dtype=torch.float64, device="cuda") for pb in probs]
+    precision = pk.FP32_BASIS if args.precision == "fp32" else pk.FP64
+    t0 = time.perf_counter()
+    plan = pk.Plan(As, [pb.p for pb in probs], [pb.t for pb in probs], bs, us, tol=probs[0].tol,
+                   precision=precision, workgroups=args.workgroups,
+                   plan_opts=pk.default_plan_opts(autotune=0 if args.no_tune else 1, graph=1))
+    create_s = time.perf_counter() - t0
+    info = plan.info()
+    for _ in range(max(1, args.warmup)):
+        plan.execute()
+    torch.cuda.synchronize()
+    st = plan.stats()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.execute(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    plan.stats()   # raises on a device-side error of the timed runs
+    nbytes = sum(s["bytes"] for s in st)
+    achieved = nbytes / (ms / 1e3) / 1e9
+    line = {
+        "metric": "phipm solves/s (adaptive Krylov phi-function solve to t_end) and HBM GB/s",
+        "value": len(probs) / (ms / 1e3),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == pk.FP64 else "f32-basis/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOADS["convdiff2d-batch256"][1],
+            "instances": len(probs), "rows": int(sum(pb.n for pb in probs)),
+            "nnz": int(sum(pb.A.nnz for pb in probs)),
+            "plan": {k: info[k] for k in ("teams", "class_size", "class_teams", "graph",
+                                          "cooperative", "candidates", "max_team", "alpha",
+                                          "tuned_ms", "default_ms")},
+            "plan_create_s": create_s,
+            "solve_stats": {"steps": sum(s["steps"] for s in st),
+                            "rejected": sum(s["rejected"] for s in st),
+                            "matvecs": sum(s["matvecs"] for s in st),
+                            "fp64_fallbacks": sum(s["fp64_fallback"] for s in st)},
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_batch (persistent batched solver)",
+            "algorithmic_bytes_per_launch": nbytes,
+        },
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_batch(probs, st)
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +261,9 @@ def main():
     ap.add_argument("--workload", default="convdiff2d-512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
+                    help="basis precision (default: the workload's)")
+    ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (3 times), so that "
                          "HBM byte counters can be scaled against a known transfer")
@@ -109,11 +287,19 @@ def main():
                           "launches": 3}), flush=True)
         return
 
+    if args.precision is None:
+        args.precision = WORKLOADS[args.workload][2]
+    if args.workload == "convdiff2d-batch256":
+        run_batch(args)
+        return
+    if args.workload == "reaction2d-1024-calls":
+        run_calls(args)
+        return
     pb = build_problem(args.workload)
     A = pk.DeviceCSR(pb.A, device="cuda")
     b = torch.as_tensor(np.ascontiguousarray(pb.b.T), device="cuda")
     u = torch.empty(pb.n, dtype=torch.float64, device="cuda")
-    precision = pk.FP32_BASIS if WORKLOADS[args.workload][2] == "fp32" else pk.FP64
+    precision = pk.FP32_BASIS if args.precision == "fp32" else pk.FP64
     solver = pk.Solver(A, pb.p, tol=pb.tol, precision=precision, workgroups=args.workgroups,
                        validate=1)
     st = None

@@ -76,10 +76,26 @@ typedef struct {
   int64_t max_attempts;  /* limit on attempts (accepted + rejected); default 1e6 */
   int32_t workgroups;    /* 0: library choice; else workgroups cooperating on the solve */
   int32_t validate;      /* 1 (default): check CSR structure and finiteness on the device */
+  const float* proposer; /* device, PHIPM_MLP_PARAMS floats: learned (tau, m) proposer that
+                            seeds every step (see phipm_mlp_*); NULL (default): plain
+                            step control.  The error estimate still accepts or rejects
+                            every attempt and Algorithm 4 handles rejections. */
+  double* history;       /* device, 4 doubles {tau, m, omega, valid}, in/out, or NULL: when
+                            valid, the first step starts from the stored (tau, m) instead of
+                            eq. tau_0 and m_init (warm start across calls); on success the
+                            call stores the proposal for the step after its last one */
+  void* trace;           /* device, trace_cap phipm_trace_step records, or NULL: one record
+                            per accepted step (training data of the proposer) */
+  int32_t trace_cap;
+  int32_t pad_;
 } phipm_opts;
 
 #define PHIPM_M_CAP 128
 #define PHIPM_P_MAX 8
+#define PHIPM_MLP_IN 12
+#define PHIPM_MLP_HIDDEN 64
+#define PHIPM_MLP_OUT 2
+#define PHIPM_MLP_PARAMS 5122
 
 /* The four counters of the paper's stats output (Sect. 3.5) and extras. */
 typedef struct {
@@ -105,7 +121,9 @@ typedef struct {
   int32_t fp64_fallback;       /* FP32 basis: 1 if the estimate exceeded 2 tol max(1, ||u||)
                                   and the solve was repeated with the FP64 basis; the
                                   counters then include both runs */
-  int32_t pad2_;
+  int32_t trace_len;           /* accepted steps offered to the trace (records beyond
+                                  trace_cap are dropped) */
+  int64_t proposals;           /* steps seeded by the proposer */
 } phipm_stats;
 
 void phipm_default_opts(phipm_opts* opts);
@@ -203,7 +221,9 @@ void phipm_default_plan_opts(phipm_plan_opts* popts);
  *   b   device pointers, n_i x (p_i+1) column-major float64
  *   u   device pointers, n_i float64 outputs; no u_i may overlap another u_j
  *       or its b_i
- * opts applies to every instance (opts->workgroups > 0 caps the grid size).
+ * opts applies to every instance (opts->workgroups > 0 caps the grid size;
+ * opts->proposer is shared by all instances; opts->history and opts->trace
+ * are ignored).
  * Work during creation (norms, tuning runs) is enqueued on `stream` and
  * synchronised.  Returns PHIPM_OK and *plan, or an error (PHIPM_EINVAL,
  * PHIPM_ENONFINITE for a non-finite t_i, PHIPM_ENOMEM, PHIPM_EHIP,
@@ -244,6 +264,100 @@ int phipm_batched(int count, const phipm_csr* A, const int32_t* p, const double*
 int phipm_batch_layout(int count, const double* cost, int workgroups, int max_team,
                        double alpha, int32_t* team_size, int32_t* team_class, int32_t* nteams,
                        int32_t* order, int32_t* qbeg, int32_t* nclasses);
+
+/* ------------------------------------------------------------------------
+ * Learned (tau, m) proposer (an addition to the paper's method, which it does
+ * not change: it only replaces the starting point of each step).
+ *
+ * Network: FP32 multilayer perceptron 12 -> 64 -> 64 -> 2, GELU (tanh form)
+ * after both hidden layers.  Parameters (PHIPM_MLP_PARAMS floats, in order):
+ * W1[64][12] b1[64] W2[64][64] b2[64] W3[2][64] b3[2].  Inputs (computed by
+ * the solver at the start of a step; all clipped to a few decades):
+ *   0 log10(||A||_inf t_end)       1 log10(tol / max_k ||b_k||_inf)   2 p / 4
+ *   3 log10(||w_p||_2 / ||u_k||_2)  4 t_k / t_end
+ *   5 log10(tau_prev ||A||_inf)    6 m_prev / 32   7 log10(omega_prev)
+ *   8 rejections of the previous step / 4
+ *   9 log10(tau_plain ||A||_inf)   10 m_plain / 32  11 1 if Lanczos
+ * where "prev" is the last accepted step (or the warm-start history) and
+ * "plain" the plain controller's choice for this step.  Outputs:
+ * (log10(tau* ||A||_inf), m / 32) with tau* the predicted largest admissible
+ * substep; the solver attempts 0.7 tau*, kept within
+ * [tau_plain, 8 tau_plain] (and below t_end - t_k) and m within
+ * [max(1, floor(3 m_plain / 4)), min(m_max, n)]: the proposer can make a
+ * step longer than the plain controller's, never shorter, and a rejection
+ * hands the step back to Algorithm 4.
+ * ---------------------------------------------------------------------- */
+
+/* One accepted step as recorded by phipm() with opts.trace set. */
+typedef struct {
+  float features[PHIPM_MLP_IN];  /* inputs seen at the start of the step */
+  int32_t m_use;                  /* Krylov dimension of the accepted attempt */
+  int32_t m_have;                 /* basis columns available (>= m_use): with a trace the
+                                     solver extends the step's basis to m_cap = min(m_max,
+                                     n) columns after the step (extra products, counted
+                                     in the stats) */
+  int32_t p, lanczos, n, nnz, attempts, pad_;
+  double t, tau, omega, beta, anorm, t_end, tol, pad2_;
+  double H[(PHIPM_M_CAP + 1) * PHIPM_M_CAP]; /* leading (m_have+1) x m_have block of the
+                                                step's Hessenberg matrix, row-major,
+                                                row stride PHIPM_M_CAP */
+} phipm_trace_step;
+
+/* Y = MLP(X) for `rows` rows (device: X rows x 12, Y rows x 2, row-major)
+ * with the solver's inference routine (one wavefront per row). */
+int phipm_mlp_forward(const float* params, const float* X, int rows, float* Y,
+                      phipm_stream_t stream);
+
+/* Gradient of the loss L = 1/(2 rows) sum_r sum_o (MLP(X)_ro - T_ro)^2 with
+ * respect to the parameters (device: grad PHIPM_MLP_PARAMS floats, loss 1
+ * float).  One workgroup, deterministic order. */
+int phipm_mlp_grad(const float* params, const float* X, const float* T, int rows, float* grad,
+                   float* loss, phipm_stream_t stream);
+
+/* Train in place with Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate
+ * lr) on minibatches of `batch` (1..64) consecutive rows, `epochs` passes in
+ * row order; adam_m / adam_v (device, PHIPM_MLP_PARAMS floats) are the moment
+ * estimates and step0 the number of updates already made with them.
+ * loss (device, epochs floats) receives each epoch's mean loss. */
+int phipm_mlp_train(float* params, float* adam_m, float* adam_v, const float* X, const float* T,
+                    int rows, int batch, int epochs, float lr, int step0, float* loss,
+                    phipm_stream_t stream);
+
+/* Time model of one step on the device, used by hindsight labels in place
+ * of the flop count of eq. 4: a step with Krylov dimension m costs
+ *   (3m + max(p, 1) + 2) sync_s                          team barriers
+ * + bytes(m) / min(bw_bytes_per_s, G wg_bytes_per_s)    streaming phases
+ * + expm_s[m + p + 1]                                   small exponential
+ * with G = min(workgroups, ceil(n / 1024)), sync_s replaced by sync1_s when
+ * G = 1, and bytes(m) the solver's algorithmic bytes in float64 (s = 8,
+ * S = (s + 4) nnz + 4 (n + 1) + 2 s n per CSR product):
+ *   p S + sum_{j=1..p} s n (p - j + 1)              w-recurrence
+ * + sum_{j=0..m-1} [S + (4 K_j + 8) s n]            Krylov steps, K_j = j + 1
+ *                                                   (Arnoldi), min(j + 1, 2)
+ *                                                   (Lanczos)
+ * + 2 s n + s n max(p + 1, 1) + (m + 1) s n         corrector vector, update */
+typedef struct {
+  double sync_s;          /* one team barrier with G > 1 workgroups */
+  double sync1_s;         /* one barrier of a single workgroup */
+  double bw_bytes_per_s;  /* streaming bandwidth of the whole grid */
+  double wg_bytes_per_s;  /* streaming bandwidth of one workgroup */
+  int32_t workgroups;     /* grid size of the solver */
+  int32_t pad_;
+  double expm_s[PHIPM_M_CAP + PHIPM_P_MAX + 2]; /* time of the exponential of order N */
+} phipm_label_costs;
+
+/* Hindsight labels of recorded steps: for m' in {1..16, 20, 24, ...,
+ * m_have} (and m_have) the largest tau in [tau/4096, t_end - t] with
+ * omega(tau, m') <= 0.8 (bisection on log tau with the solver's small
+ * exponential), and the (tau*, m') of least cost per unit time: C1(m') / tau*
+ * (eq. 4, eq. 8) when costs is NULL, else the time model above divided by
+ * tau*.  Device outputs: X (count x 12, the recorded features) and T
+ * (count x 2: log10(tau* ||A||_inf), m'/32).  workspace: device,
+ * >= phipm_label_workspace_bytes(count); costs: host, may be NULL. */
+size_t phipm_label_workspace_bytes(int count);
+int phipm_label_steps(const phipm_trace_step* records, int count, float* X, float* T,
+                      void* workspace, size_t ws_bytes, const phipm_label_costs* costs,
+                      phipm_stream_t stream);
 
 const char* phipm_status_string(int status);
 

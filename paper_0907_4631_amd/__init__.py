@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libphipm.so")
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EMAXSTEPS, EUNSUPPORTED, EABORT = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_BASIS = 0, 1
 M_CAP, P_MAX = 128, 8
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 12, 64, 2, 5122
 
 
 class PhipmError(RuntimeError):
@@ -36,7 +37,8 @@ class Opts(C.Structure):
                 ("m_max", C.c_int32), ("precision", C.c_int32), ("adapt_m", C.c_int32),
                 ("corrector", C.c_int32), ("tau_fixed", C.c_double),
                 ("max_attempts", C.c_int64), ("workgroups", C.c_int32),
-                ("validate", C.c_int32)]
+                ("validate", C.c_int32), ("proposer", C.c_void_p), ("history", C.c_void_p),
+                ("trace", C.c_void_p), ("trace_cap", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -46,10 +48,28 @@ class Stats(C.Structure):
                 ("workgroups", C.c_int32), ("anorm", C.c_double), ("setup_flags", C.c_int32),
                 ("pad_", C.c_int32), ("bytes", C.c_double), ("phi_ratio_max", C.c_double),
                 ("precision_rejects", C.c_int64), ("fp32_error_estimate", C.c_double),
-                ("fp64_fallback", C.c_int32), ("pad2_", C.c_int32)]
+                ("fp64_fallback", C.c_int32), ("trace_len", C.c_int32),
+                ("proposals", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TraceStep(C.Structure):
+    """phipm_trace_step (records live in device memory; this describes them)."""
+    _fields_ = [("features", C.c_float * MLP_IN), ("m_use", C.c_int32), ("m_have", C.c_int32),
+                ("p", C.c_int32), ("lanczos", C.c_int32), ("n", C.c_int32), ("nnz", C.c_int32),
+                ("attempts", C.c_int32), ("pad_", C.c_int32), ("t", C.c_double),
+                ("tau", C.c_double), ("omega", C.c_double), ("beta", C.c_double),
+                ("anorm", C.c_double), ("t_end", C.c_double), ("tol", C.c_double),
+                ("pad2_", C.c_double), ("H", C.c_double * ((M_CAP + 1) * M_CAP))]
+
+
+class LabelCosts(C.Structure):
+    """phipm_label_costs: device time model of one step (hindsight labels)."""
+    _fields_ = [("sync_s", C.c_double), ("sync1_s", C.c_double), ("bw_bytes_per_s", C.c_double),
+                ("wg_bytes_per_s", C.c_double), ("workgroups", C.c_int32), ("pad_", C.c_int32),
+                ("expm_s", C.c_double * (M_CAP + P_MAX + 2))]
 
 
 class PlanOpts(C.Structure):
@@ -79,7 +99,8 @@ EXPORTS = ["phipm_default_opts", "phipm_workspace_bytes", "phipm", "phipm_last_s
            "phipm_spmv", "phipm_expm", "phipm_krylov", "phipm_status_string",
            "phipm_default_plan_opts", "phipm_plan_create", "phipm_plan_execute",
            "phipm_plan_stats", "phipm_plan_get_info", "phipm_plan_destroy", "phipm_batched",
-           "phipm_batch_layout"]
+           "phipm_batch_layout", "phipm_mlp_forward", "phipm_mlp_grad", "phipm_mlp_train",
+           "phipm_label_workspace_bytes", "phipm_label_steps"]
 
 
 def lib():
@@ -129,6 +150,18 @@ def lib():
         L.phipm_batch_layout.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int,
                                          C.c_double, ip, ip, ip, ip, ip, ip]
         L.phipm_batch_layout.restype = C.c_int
+        L.phipm_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp]
+        L.phipm_mlp_forward.restype = C.c_int
+        L.phipm_mlp_grad.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp]
+        L.phipm_mlp_grad.restype = C.c_int
+        L.phipm_mlp_train.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float,
+                                      C.c_int, vp, vp]
+        L.phipm_mlp_train.restype = C.c_int
+        L.phipm_label_workspace_bytes.argtypes = [C.c_int]
+        L.phipm_label_workspace_bytes.restype = C.c_size_t
+        L.phipm_label_steps.argtypes = [vp, C.c_int, vp, vp, vp, C.c_size_t,
+                                        C.POINTER(LabelCosts), vp]
+        L.phipm_label_steps.restype = C.c_int
         _lib = L
     return _lib
 
@@ -380,3 +413,83 @@ def batch_layout(cost, workgroups: int, max_team: int, alpha: float):
         raise PhipmError(rc, "phipm_batch_layout")
     return {"team_size": ts[:nt.value].copy(), "team_class": tc[:nt.value].copy(),
             "order": order[:count].copy(), "qbeg": qbeg[:nc.value + 1].copy()}
+
+
+# ------------------------------------------------------------ proposer kernels
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _check_f32(*ts):
+    torch = _torch()
+    for t in ts:
+        if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+            raise TypeError("expected contiguous float32 device tensors")
+
+
+def mlp_forward(params, X, stream=None):
+    """Y = MLP(X), X: (rows, 12) float32 device tensor."""
+    torch = _torch()
+    _check_f32(params, X)
+    rows = X.shape[0]
+    Y = torch.empty((rows, MLP_OUT), dtype=torch.float32, device=X.device)
+    rc = lib().phipm_mlp_forward(_ptr(params), _ptr(X), rows, _ptr(Y), _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_mlp_forward")
+    return Y
+
+
+def mlp_grad(params, X, T, stream=None):
+    """(gradient, loss) of the mean squared error loss on (X, T)."""
+    torch = _torch()
+    _check_f32(params, X, T)
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    rc = lib().phipm_mlp_grad(_ptr(params), _ptr(X), _ptr(T), X.shape[0], _ptr(g), _ptr(loss),
+                              _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_mlp_grad")
+    return g, loss
+
+
+def mlp_train(params, adam_m, adam_v, X, T, epochs, lr=1e-3, batch=64, step0=0, stream=None):
+    """Adam training in place; returns the per-epoch mean losses (device tensor)."""
+    torch = _torch()
+    _check_f32(params, adam_m, adam_v, X, T)
+    loss = torch.empty(max(1, epochs), dtype=torch.float32, device=X.device)
+    rc = lib().phipm_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), _ptr(X), _ptr(T),
+                               X.shape[0], int(batch), int(epochs), float(lr), int(step0),
+                               _ptr(loss), _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_mlp_train")
+    return loss[:epochs]
+
+
+def label_steps(trace, count, costs: LabelCosts | None = None, stream=None):
+    """Hindsight labels of `count` recorded steps in the device buffer `trace`
+    (cost per unit time from eq. 4, or from the time model `costs`).
+    Returns (X, T) float32 device tensors."""
+    torch = _torch()
+    X = torch.empty((max(1, count), MLP_IN), dtype=torch.float32, device=trace.device)
+    T = torch.empty((max(1, count), MLP_OUT), dtype=torch.float32, device=trace.device)
+    nb = lib().phipm_label_workspace_bytes(int(count))
+    ws = torch.empty(nb, dtype=torch.uint8, device=trace.device)
+    rc = lib().phipm_label_steps(_ptr(trace), int(count), _ptr(X), _ptr(T), _ptr(ws), nb,
+                                 C.byref(costs) if costs is not None else None,
+                                 _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_label_steps")
+    return X[:count], T[:count]
+
+
+def alloc_trace(cap, device="cuda"):
+    """Device buffer for `cap` phipm_trace_step records."""
+    torch = _torch()
+    return torch.empty(cap * C.sizeof(TraceStep), dtype=torch.uint8, device=device)
+
+
+def trace_records(trace, count):
+    """Copy `count` records to the host as TraceStep structures."""
+    raw = trace[: count * C.sizeof(TraceStep)].cpu().numpy().tobytes()
+    return [TraceStep.from_buffer_copy(raw, i * C.sizeof(TraceStep)) for i in range(count)]

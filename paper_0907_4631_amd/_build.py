@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "phipm_api.hip"), os.path.join(HERE, "csrc", "batch.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("phipm_api.hip", "batch.hip", "mlp.hip")]
 LIB = os.path.join(HERE, "libphipm.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -67,6 +67,7 @@ struct BatchArgs {
   long long max_attempts;
   int ncls, symm, m_init, m_max, adapt_m, corrector, validate, pad;
   unsigned long long spin;
+  const float* proposer;
 };
 
 // Clears the barrier flags, the queue heads and the abort word (a kernel, so
@@ -170,6 +171,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
     P.adapt_m = a.adapt_m;
     P.corrector = a.corrector;
     P.validate = a.validate;
+    P.proposer = a.proposer;
     w.stats = a.stats + id;
     if (rank == 0 && threadIdx.x == 0) a.clk[2 * id] = wall_clock64();
     solve_mixed<T>(tm, P, w, sh);
@@ -421,6 +423,7 @@ int set_layout(phipm_plan* pl, const TeamLayout& L, hipStream_t stream) {
   a.corrector = pl->opts.corrector;
   a.validate = pl->opts.validate;
   a.spin = pl->spin;
+  a.proposer = pl->opts.proposer;
   pl->layout = L;
   return PHIPM_OK;
 }

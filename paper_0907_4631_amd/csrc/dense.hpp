@@ -14,8 +14,10 @@ constexpr int DENSE_LDS = 17408;  // doubles of LDS available to the dense routi
 // C = A B for N x N row-major matrices in device memory (an L2-resident
 // scratch).  When both operands fit, A is staged transposed and B as is in
 // LDS, zero-padded to a multiple of 4, and every thread accumulates a 4 x 4
-// block of C in registers from 16-byte LDS reads; otherwise one output entry
-// per thread straight from memory.
+// block of C in registers from 16-byte LDS reads.  Up to N = 128 (at most one
+// 4 x 4 block per thread) the same runs over panels of MM_KC values of k
+// staged in turn; beyond that, one output entry per thread straight from
+// memory.
 __device__ __forceinline__ void wg_matmul(int N, const double* __restrict__ A,
                                           const double* __restrict__ B, double* __restrict__ C,
                                           double* L) {
@@ -62,6 +64,55 @@ __device__ __forceinline__ void wg_matmul(int N, const double* __restrict__ A,
     __syncthreads();
     return;
   }
+  constexpr int MM_KC = 32;
+  if ((N4 >> 2) * (N4 >> 2) <= BLOCK && 2 * MM_KC * N4 <= DENSE_LDS) {
+    double* At = L;              // At[kk][i] = A[i][k0 + kk]
+    double* Bs = L + MM_KC * N4; // Bs[kk][j] = B[k0 + kk][j]
+    const int nb = N4 >> 2;
+    const int t = threadIdx.x;
+    const bool mine = t < nb * nb;
+    const int ib = mine ? t / nb : 0, jb = mine ? t - ib * nb : 0;
+    const int i0 = 4 * ib, j0 = 4 * jb;
+    double c[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c[a][b] = 0.0;
+    for (int k0 = 0; k0 < N; k0 += MM_KC) {
+      const int kc = N - k0 < MM_KC ? N - k0 : MM_KC;
+      __syncthreads();  // the previous panel has been consumed
+      for (int e = threadIdx.x; e < MM_KC * N4; e += BLOCK) {
+        const int kk = e / N4, r = e - kk * N4;
+        const bool in = r < N && kk < kc;
+        At[e] = in ? A[r * N + k0 + kk] : 0.0;
+        Bs[e] = in ? B[(k0 + kk) * N + r] : 0.0;
+      }
+      __syncthreads();
+      if (mine) {
+        for (int kk = 0; kk < kc; ++kk) {
+          const double2 x01 = *reinterpret_cast<const double2*>(At + kk * N4 + i0);
+          const double2 x23 = *reinterpret_cast<const double2*>(At + kk * N4 + i0 + 2);
+          const double2 y01 = *reinterpret_cast<const double2*>(Bs + kk * N4 + j0);
+          const double2 y23 = *reinterpret_cast<const double2*>(Bs + kk * N4 + j0 + 2);
+          const double x[4] = {x01.x, x01.y, x23.x, x23.y};
+          const double y[4] = {y01.x, y01.y, y23.x, y23.y};
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) c[a][b] = fma(x[a], y[b], c[a][b]);
+        }
+      }
+    }
+    if (mine) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (i0 + a < N && j0 + b < N) C[(i0 + a) * N + j0 + b] = c[a][b];
+    }
+    __syncthreads();
+    return;
+  }
   for (int e = threadIdx.x; e < NN; e += BLOCK) {
     const int i = e / N, j = e - i * N;
     const double* a = A + i * N;
@@ -82,60 +133,83 @@ __device__ __forceinline__ unsigned pivot_key(double v, int row) {
 }
 
 // Solve P X = Q in place (X overwrites Q) by Gauss-Jordan elimination with
-// partial pivoting.  When [P | Q] fits in LDS (N <= 128), stored by columns,
-// lanes own rows (i and i+64) and waves own columns, so every column is
-// updated by a single wave: the pivot row and row k are read in place (LDS
-// operations of one wave complete in order) and the row exchange is folded
-// into the update.  Wave 0, which owns column k+1, posts the candidates for
-// the next pivot with LDS atomic max on pivot keys.  One barrier per column.
-__device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q, double* L) {
-  __shared__ unsigned s_key[2];
+// partial pivoting.  For N <= 128 the system is stored by columns, lanes own
+// rows (i and i+64) and waves own columns, so every column is updated by a
+// single wave: the pivot row and row k are read in place (each lane's update
+// depends on them, so its loads complete before its stores) and the row
+// exchange is folded into the update.  Wave 0, which owns column k+1, posts
+// the candidates for the next pivot with LDS atomic max on pivot keys.  One
+// barrier per column.  [P | Q] lives in LDS when it fits; otherwise P does
+// and Q is kept by columns in the device scratch Wk (N x N doubles, L2
+// resident).
+// Elimination over the columns of [P | Q] for the layouts of wg_gauss_jordan:
+// P by columns at M (LDS, stride ld), Q by columns at G (stride ldq; LDS
+// when QLDS, device memory otherwise).  Each pointer keeps one address space
+// so that LDS columns are accessed with LDS instructions.
+template <bool QLDS>
+__device__ __forceinline__ void gj_eliminate(int N, double* M, int ld, double* G, int ldq,
+                                             unsigned* s_key) {
   const int tid = threadIdx.x;
   const int lane = tid % WAVE, wv = tid / WAVE;
-  const int W2 = 2 * N;
+  const int i0 = lane, i1 = lane + WAVE;
+  const bool r0 = i0 < N, r1 = i1 < N;
+  for (int k = 0; k < N; ++k) {
+    const int piv = 255 - (int)(s_key[k & 1] & 0xffu);
+    if (tid == 0) s_key[(k + 1) & 1] = 0u;
+    const double* colk = M + k * ld;
+    const double inv = 1.0 / colk[piv];
+    const double kk = colk[k];
+    const double f0 = r0 ? colk[i0] : 0.0;
+    const double f1 = r1 ? colk[i1] : 0.0;
+    auto update = [&](double* col, bool cand) {
+      const double pr = col[piv] * inv;
+      const double kj = col[k];
+      const double a0 = r0 ? col[i0] : 0.0;
+      const double a1 = r1 ? col[i1] : 0.0;
+      const double v0 = i0 == k ? pr : (i0 == piv ? kj - kk * pr : a0 - f0 * pr);
+      const double v1 = i1 == k ? pr : (i1 == piv ? kj - kk * pr : a1 - f1 * pr);
+      if (cand) {  // candidates for the next pivot: rows > k
+        if (r0 && i0 > k) atomicMax(&s_key[(k + 1) & 1], pivot_key(v0, i0));
+        if (r1 && i1 > k) atomicMax(&s_key[(k + 1) & 1], pivot_key(v1, i1));
+      }
+      if (r0) col[i0] = v0;
+      if (r1) col[i1] = v1;
+    };
+#pragma unroll 4
+    for (int j = k + 1 + wv; j < N; j += NWAVES) update(M + j * ld, j == k + 1);
+#pragma unroll 4
+    for (int j = wv; j < N; j += NWAVES) update(G + j * ldq, false);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q, double* L,
+                                                double* Wk) {
+  __shared__ unsigned s_key[2];
+  const int tid = threadIdx.x;
   const int ld = (N + 1) & ~1;  // column stride of the transposed system
-  if (N <= 2 * WAVE && W2 * ld <= DENSE_LDS) {
-    double* M = L;  // [P | Q] stored by columns: entry (i, j) at M[j * ld + i]
+  if (N <= 2 * WAVE && N * ld <= DENSE_LDS) {
+    const bool all_lds = 2 * N * ld <= DENSE_LDS;
+    double* M = L;  // P stored by columns: entry (i, j) at M[j * ld + i]
     if (tid == 0) { s_key[0] = 0u; s_key[1] = 0u; }
     for (int e = tid; e < N * N; e += BLOCK) {
       const int i = e / N, j = e - i * N;
       M[j * ld + i] = P[e];
-      M[(N + j) * ld + i] = Q[e];
+    }
+    if (all_lds) {
+      for (int e = tid; e < N * N; e += BLOCK) L[N * ld + (e % N) * ld + e / N] = Q[e];
+    } else {
+      for (int e = tid; e < N * N; e += BLOCK) Wk[(e % N) * N + e / N] = Q[e];
     }
     __syncthreads();
     for (int i = tid; i < N; i += BLOCK) atomicMax(&s_key[0], pivot_key(M[i], i));
     __syncthreads();
-    const int i0 = lane, i1 = lane + WAVE;
-    const bool r0 = i0 < N, r1 = i1 < N;
-    for (int k = 0; k < N; ++k) {
-      const int piv = 255 - (int)(s_key[k & 1] & 0xffu);
-      if (tid == 0) s_key[(k + 1) & 1] = 0u;
-      const double* colk = M + k * ld;
-      const double inv = 1.0 / colk[piv];
-      const double kk = colk[k];
-      const double f0 = r0 ? colk[i0] : 0.0;
-      const double f1 = r1 ? colk[i1] : 0.0;
-#pragma unroll 4
-      for (int j = k + 1 + wv; j < W2; j += NWAVES) {
-        double* col = M + j * ld;
-        const double pr = col[piv] * inv;
-        const double kj = col[k];
-        const double a0 = r0 ? col[i0] : 0.0;
-        const double a1 = r1 ? col[i1] : 0.0;
-        const double v0 = i0 == k ? pr : (i0 == piv ? kj - kk * pr : a0 - f0 * pr);
-        const double v1 = i1 == k ? pr : (i1 == piv ? kj - kk * pr : a1 - f1 * pr);
-        if (j == k + 1 && j < N) {  // candidates for the next pivot: rows > k
-          if (r0 && i0 > k) atomicMax(&s_key[(k + 1) & 1], pivot_key(v0, i0));
-          if (r1 && i1 > k) atomicMax(&s_key[(k + 1) & 1], pivot_key(v1, i1));
-        }
-        if (r0) col[i0] = v0;
-        if (r1) col[i1] = v1;
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < N * N; e += BLOCK) {
-      const int i = e / N, j = e - i * N;
-      Q[e] = M[(N + j) * ld + i];
+    if (all_lds) gj_eliminate<true>(N, M, ld, L + N * ld, ld, s_key);
+    else gj_eliminate<false>(N, M, ld, Wk, N, s_key);
+    if (all_lds) {
+      for (int e = tid; e < N * N; e += BLOCK) Q[e] = L[N * ld + (e % N) * ld + e / N];
+    } else {
+      for (int e = tid; e < N * N; e += BLOCK) Q[e] = Wk[(e % N) * N + e / N];
     }
     __syncthreads();
     return;
@@ -266,7 +340,7 @@ __device__ __forceinline__ double* wg_expm(int N, double* S, double* L, double* 
     Q[e] = ev + U[e];
   }
   __syncthreads();
-  wg_gauss_jordan(N, P, Q, L);
+  wg_gauss_jordan(N, P, Q, L, X2);  // X2 is free scratch from here on
   double* cur = Q;
   double* nxt = U;
   for (int k = 0; k < s; ++k) {

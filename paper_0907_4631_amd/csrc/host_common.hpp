@@ -6,12 +6,19 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstddef>
 #include <cstring>
 
 #include "../../include/phipm.h"
 #include "solver.hpp"
 
 namespace pkr {
+
+// device-side mirrors of the C ABI structures
+static_assert(sizeof(Stats) == sizeof(phipm_stats), "Stats mirrors phipm_stats");
+static_assert(sizeof(TraceStep) == sizeof(phipm_trace_step), "TraceStep mirrors phipm_trace_step");
+static_assert(offsetof(TraceStep, H) == offsetof(phipm_trace_step, H), "trace layout");
+static_assert(offsetof(Stats, proposals) == offsetof(phipm_stats, proposals), "stats layout");
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 inline long long pad64(long long x) { return (x + 63) / 64 * 64; }
@@ -57,7 +64,8 @@ inline bool opts_ok(const phipm_opts* o) {
   return o && o->tol > 0.0 && std::isfinite(o->tol) && o->m_init >= 1 && o->m_max >= o->m_init &&
          o->m_max <= PHIPM_M_CAP && (o->symm >= -1 && o->symm <= 1) &&
          (o->precision == PHIPM_FP64 || o->precision == PHIPM_FP32_BASIS) && o->max_attempts >= 1 &&
-         o->workgroups >= 0 && std::isfinite(o->tau_fixed) && o->tau_fixed >= 0.0;
+         o->workgroups >= 0 && std::isfinite(o->tau_fixed) && o->tau_fixed >= 0.0 &&
+         o->trace_cap >= 0 && (o->trace_cap == 0 || o->trace);
 }
 
 inline bool csr_ok(const phipm_csr* A) {
@@ -89,7 +97,8 @@ inline void copy_stats(const Stats& hs, int status, phipm_stats* s) {
   s->precision_rejects = hs.prec_rejects;
   s->fp32_error_estimate = hs.fp32_err;
   s->fp64_fallback = hs.fp64_fallback;
-  s->pad2_ = 0;
+  s->trace_len = hs.trace_len;
+  s->proposals = hs.proposals;
 }
 
 }  // namespace pkr

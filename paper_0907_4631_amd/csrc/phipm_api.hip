@@ -249,6 +249,10 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   P.adapt_m = o->adapt_m;
   P.corrector = o->corrector;
   P.validate = o->validate;
+  P.proposer = o->proposer;
+  P.history = o->history;
+  P.trace = static_cast<TraceStep*>(o->trace);
+  P.trace_cap = o->trace ? o->trace_cap : 0;
 
   TeamCtl* ctl = reinterpret_cast<TeamCtl*>(ws + L.ctl);
   double* part = reinterpret_cast<double*>(ws + L.part);

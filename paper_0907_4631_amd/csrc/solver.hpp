@@ -21,6 +21,7 @@
 #pragma once
 #include "controller.hpp"
 #include "dense.hpp"
+#include "proposer.hpp"
 #include "spmv.hpp"
 #include "team.hpp"
 
@@ -48,6 +49,22 @@ struct Problem {
   double tau_fixed;
   long long max_attempts;
   int symm, m_init, m_max, adapt_m, corrector, validate;
+  const float* proposer;    // MLP parameters, or null
+  double* history;          // {tau, m, omega, valid} carried across calls, or null
+  struct TraceStep* trace;  // per accepted step records, or null
+  int trace_cap, pad;
+};
+
+// One accepted step as recorded for training the proposer (mirrors
+// phipm_trace_step): the features seen at the start of the step, the step's
+// outcome and the Krylov data that hindsight labelling needs (the leading
+// (m_have+1) x m_have block of H, row-major with stride M_CAP).
+struct TraceStep {
+  float feat[MLP_IN];
+  int m_use, m_have, p, lanczos;
+  int n, nnz, attempts, pad;
+  double t, tau, omega, beta, anorm, t_end, tol, pad_d;
+  double H[(M_CAP + 1) * M_CAP];
 };
 
 struct Stats {              // mirrors phipm_stats
@@ -60,7 +77,8 @@ struct Stats {              // mirrors phipm_stats
   double rho_max;
   long long prec_rejects;
   double fp32_err;          // accumulated FP32 rounding estimate (absolute)
-  int fp64_fallback, pad2;
+  int fp64_fallback, trace_len;
+  long long proposals;      // steps seeded by the proposer
 };
 
 struct State {
@@ -72,6 +90,12 @@ struct State {
   long long prec_rejects;   // attempts rejected for FP32 rounding
   double fp32_err;          // sum over accepted steps of the FP32 rounding estimate
   int need_fp64, pad3;      // the FP32 estimate ran over budget: solve again in FP64
+  // step history (proposer features, warm start, trace)
+  float feat[MLP_IN];       // features at the start of the current step
+  double tau_prev, omega_prev, tau_prop;
+  int m_prev, m_prop, step_rejects, prev_rejects;
+  long long proposals;
+  int trace_len, pad4;
   int setup_flags, pad0;
   double eps, omega, knorm;
   int m, m_cap, lanczos, zero_path;
@@ -260,6 +284,8 @@ struct DecideArgs {
   double tol, tau_fixed, nnz, n;
   long long max_attempts;
   int p, adapt_m, corrector, have, broke, fp32;
+  TraceStep* trace;
+  int trace_cap, pad;
 };
 
 // Unit roundoff of the FP32 basis.
@@ -407,7 +433,34 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
     st->knorm = knorm;
     st->accept = accept;
     st->m_use = m_use;
+    if (accept && a.trace && beta > 0.0 && have > 0 && st->trace_len < a.trace_cap) {
+      TraceStep* r = a.trace + st->trace_len;
+      for (int i = 0; i < MLP_IN; ++i) r->feat[i] = st->feat[i];
+      r->m_use = m_use;
+      r->m_have = have;
+      r->p = p;
+      r->lanczos = st->lanczos;
+      r->n = (int)a.n;
+      r->nnz = (int)a.nnz;
+      r->attempts = st->step_rejects + 1;
+      r->pad = 0;
+      r->t = t;
+      r->tau = tau;
+      r->omega = omega;
+      r->beta = beta;
+      r->anorm = st->anorm;
+      r->t_end = t_end;
+      r->tol = a.tol;
+      r->pad_d = 0.0;
+    }
     if (accept) {
+      st->tau_prev = tau;
+      st->m_prev = m_use;
+      st->omega_prev = omega;
+      st->prev_rejects = st->step_rejects;
+      st->step_rejects = 0;
+      st->tau_prop = tau_next;
+      st->m_prop = m_next;
       double f = 1.0;
       for (int j = 0; j < p; ++j) {
         st->coef[j] = f;
@@ -427,6 +480,7 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       st->tau = tau_next < t_end - tn ? tau_next : t_end - tn;
     } else {
       st->rejected += 1;
+      st->step_rejects += 1;
       st->tau = tau_next;
       st->m = m_next;
     }
@@ -434,6 +488,70 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       st->status = ST_EMAXSTEPS;
       st->done = 1;
       st->accept = 0;
+    }
+  }
+  __syncthreads();
+}
+
+// Fraction of the proposer's predicted boundary substep that is attempted.
+constexpr double PROPOSER_TAU_MARGIN = 0.7;
+
+// Start of a step (workgroup 0 only): the features of eq. step's next
+// substep and, with a proposer, its proposal for (tau, m).  The proposal is
+// kept within [tau_plain, 8 tau_plain] and [floor(3 m_plain / 4), m_cap];
+// the error estimate still decides every attempt.
+__device__ __noinline__ void step_start(const float* proposer, double tol, int p, int adapt_m,
+                                       double tau_fixed, State* st, double beta) {
+  __shared__ float s_x[MLP_IN];
+  __shared__ float s_h[MLP_H];
+  __shared__ float s_y[MLP_OUT];
+  if (threadIdx.x == 0) {
+    const double an = st->anorm, te = st->t_end;
+    float x[MLP_IN];
+    x[F_STIFF] = log10c(an * te, -6.f, 12.f);
+    x[F_RTOL] = log10c(tol / (st->bnorm > 0.0 ? st->bnorm : 1.0), -20.f, 4.f);
+    x[F_P] = 0.25f * (float)p;
+    x[F_SEED] = log10c(beta / (st->unorm > 0.0 ? st->unorm : 1.0), -20.f, 20.f);
+    x[F_PROGRESS] = clampf((float)(st->t / te), 0.f, 1.f);
+    x[F_TAU_PREV] = log10c(st->tau_prev * an, -12.f, 12.f);
+    x[F_M_PREV] = (float)st->m_prev / 32.f;
+    x[F_OMEGA_PREV] = log10c(st->omega_prev, -12.f, 6.f);
+    x[F_REJ_PREV] = clampf(0.25f * (float)st->prev_rejects, 0.f, 4.f);
+    x[F_TAU_PLAIN] = log10c(st->tau * an, -12.f, 12.f);
+    x[F_M_PLAIN] = (float)st->m / 32.f;
+    x[F_LANCZOS] = st->lanczos ? 1.f : 0.f;
+    for (int i = 0; i < MLP_IN; ++i) {
+      st->feat[i] = x[i];
+      s_x[i] = x[i];
+    }
+  }
+  __syncthreads();
+  if (proposer) {
+    if (threadIdx.x < WAVE) mlp_forward_wave(proposer, s_x, s_h, s_y);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double an = st->anorm;
+      const double rem = st->t_end - st->t;
+      const double tp = st->tau;
+      // the network predicts the largest admissible tau (omega = gamma); the
+      // error estimate is steep in tau at large m, so aim a little below it
+      double tau =
+          (an > 0.0 && isfinite(s_y[0])) ? PROPOSER_TAU_MARGIN * pow(10.0, (double)s_y[0]) / an : tp;
+      if (!(tau > 0.0) || !isfinite(tau)) tau = tp;
+      // trust region: tau only upwards (up to 8x the plain controller's
+      // choice), m down to Algorithm 3's own lower clamp floor(3 m / 4).  A
+      // tau that is too large costs a rejection, after which Algorithm 4
+      // reduces it; a tau below the plain choice would feed back through the
+      // next step's features and could shrink the steps geometrically.
+      tau = fmin(fmax(tau, tp), 8.0 * tp);
+      if (tau > rem) tau = rem;
+      double mm = isfinite(s_y[1]) ? rint(32.0 * (double)s_y[1]) : (double)st->m;
+      mm = fmin(fmax(mm, fmax(1.0, floor(0.75 * (double)st->m))), (double)st->m_cap);
+      if (tau_fixed <= 0.0) {
+        st->tau = tau;
+        if (adapt_m) st->m = (int)mm;
+      }
+      st->proposals += 1;
     }
   }
   __syncthreads();
@@ -535,8 +653,26 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       else tau = ctrl_tau0(P.tol, st->anorm, bn, 0.5 * (double)(P.m_init + P.m_max));
       if (!(tau > 0.0) || !isfinite(tau)) tau = st->t_end;
       if (tau > st->t_end) tau = st->t_end;
+      int m0 = P.m_init < st->m_cap ? P.m_init : st->m_cap;
+      // warm start: the previous call's proposal for the step after its last
+      double om0 = 1.0;
+      if (P.history && P.history[3] > 0.0 && P.tau_fixed <= 0.0) {
+        const double ht = P.history[0];
+        const double hm = P.history[1];
+        if (ht > 0.0 && isfinite(ht)) tau = ht < st->t_end ? ht : st->t_end;
+        if (hm >= 1.0 && isfinite(hm)) m0 = (int)fmin(hm, (double)st->m_cap);
+        if (P.history[2] > 0.0 && isfinite(P.history[2])) om0 = P.history[2];
+      }
       st->tau = tau;
-      st->m = P.m_init < st->m_cap ? P.m_init : st->m_cap;
+      st->m = m0;
+      st->tau_prev = tau;
+      st->m_prev = m0;
+      st->omega_prev = om0;
+      st->tau_prop = tau;
+      st->m_prop = m0;
+      st->step_rejects = st->prev_rejects = 0;
+      st->proposals = 0;
+      st->trace_len = 0;
       st->t = 0.0;
       st->bd_tol = ldexp(st->anorm, -40);
       st->done = (st->status != ST_OK);
@@ -636,6 +772,11 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         if (!isfinite(beta)) { st->status = ST_ENONFINITE; }
       }
       if (!isfinite(beta)) goto finish;
+      // features of this step; the proposer (if any) seeds tau and m
+      if (P.proposer || P.trace) {
+        if (tm.rank == 0) step_start(P.proposer, P.tol, p, P.adapt_m, P.tau_fixed, st, beta);
+        if (P.proposer && !team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
+      }
       const double* wp = p == 0 ? P.u : w.W + (long long)(p - 1) * w.ldw;
 
       // ---- attempts of this step (Algorithm 3 inner loop)
@@ -668,7 +809,8 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         }
         if (tm.rank == 0) {
           DecideArgs da{P.tol, P.tau_fixed, (double)P.nnz, (double)n, P.max_attempts,
-                        p, P.adapt_m, P.corrector, have, broke ? 1 : 0, fp32 ? 1 : 0};
+                        p, P.adapt_m, P.corrector, have, broke ? 1 : 0, fp32 ? 1 : 0,
+                        P.trace, P.trace_cap, 0};
           decide(da, st, w.H, w.ex, sh.dense);
         }
         if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
@@ -700,6 +842,36 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         block_reduce<1>(un, RED_SUM, sh.blk);
         if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
         if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
+        if (P.trace && use_v) {
+          // training record: extend the basis (prefix-stable, tau-independent)
+          // to m_cap columns so that hindsight labels can weigh every m,
+          // then store H
+          if (!broke) {
+            const int m_ext = st->m_cap;
+            while (!broke && have < m_ext) {
+              const double h = krylov_step<T, T>(tm, P, w, valT, sgn, lanczos, have,
+                                                 (have - 1) & 1 ? w.y1 : w.y0, T(1.0 / hprev),
+                                                 rb, re, sh);
+              if (h < 0.0) return SOLVE_ABORTED;
+              ++have;
+              hprev = h;
+              if (h <= st->bd_tol || have == n) broke = true;
+            }
+          }
+          if (tm.rank == 0) {
+            const int slot = st->trace_len;
+            if (slot < P.trace_cap) {
+              double* dst = P.trace[slot].H;
+              for (int e = tid; e < (have + 1) * M_CAP; e += BLOCK) {
+                const int jj = e % M_CAP;
+                dst[e] = jj < have ? w.H[e] : 0.0;
+              }
+              if (tid == 0) P.trace[slot].m_have = have;
+            }
+            __syncthreads();
+            if (tid == 0) st->trace_len = slot + 1;
+          }
+        }
         // st->fp32_err was written before the decision's team_sync, so every
         // workgroup sees the same value and takes the same branch
         if (fp32 && !(P.tau_fixed > 0.0) &&
@@ -732,6 +904,15 @@ finish:
     o->prec_rejects = st->prec_rejects;
     o->fp32_err = st->fp32_err;
     o->fp64_fallback = 0;
+    o->trace_len = st->trace_len;
+    o->proposals = st->proposals;
+    // the next call's warm start: the proposal for the step after the last
+    if (P.history && st->status == ST_OK && st->steps > 0 && !fallback && !st->need_fp64) {
+      P.history[0] = st->tau_prop;
+      P.history[1] = (double)st->m_prop;
+      P.history[2] = st->omega_prev;
+      P.history[3] = 1.0;
+    }
   }
   return (fallback || st->need_fp64) ? SOLVE_NEEDS_FP64 : SOLVE_DONE;
 }

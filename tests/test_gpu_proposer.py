@@ -1,0 +1,235 @@
+"""GPU tests of the learned (tau, m) proposer: its kernels against the CPU
+oracle (forward pass, loss gradient, Adam update, hindsight labels), the
+trace the solver records for training, training itself, the unchanged error
+control with a proposer attached, and what the trained network gains over the
+plain step control on held-out problems."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+NP = 5122
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0907_4631_amd as pk
+    pk.lib()
+    oracle.build(force=False)
+    return pk
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def f32(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
+
+
+def random_params(seed, scale=0.3):
+    return np.random.default_rng(seed).normal(0, scale, NP).astype(np.float32)
+
+
+def test_mlp_forward_matches_oracle(pk):
+    say("mlp forward")
+    P = random_params(1)
+    X = np.random.default_rng(2).normal(0, 1.5, (137, 12)).astype(np.float32)
+    Y = pk.mlp_forward(f32(P), f32(X)).cpu().numpy()
+    R = oracle.mlp_forward(P.astype(np.float64), X.astype(np.float64))
+    assert np.all(np.abs(Y - R) <= 2e-5 * (1 + np.abs(R)))
+
+
+def test_mlp_gradient_matches_oracle_and_finite_differences(pk):
+    say("mlp gradient")
+    P = random_params(3)
+    g = np.random.default_rng(4)
+    X = g.normal(0, 1, (150, 12)).astype(np.float32)      # 64 + 64 + 22 rows
+    T = g.normal(0, 1, (150, 2)).astype(np.float32)
+    grad, loss = pk.mlp_grad(f32(P), f32(X), f32(T))
+    grad = grad.cpu().numpy().astype(np.float64)
+    P64, X64, T64 = (a.astype(np.float64) for a in (P, X, T))
+    L, G = oracle.mlp_loss_grad(P64, X64, T64)
+    assert float(loss.item()) == pytest.approx(L, rel=1e-5)
+    assert np.linalg.norm(grad - G) <= 1e-5 * np.linalg.norm(G)
+    assert np.all(np.abs(grad - G) <= 1e-5 * np.abs(G) + 1e-6 * np.abs(G).max())
+    # central differences of the FP64 loss on a sample of parameters
+    idx = np.concatenate([g.choice(NP, 48, replace=False), [768, 832, NP - 2, NP - 1]])
+    h = 1e-5
+    for i in idx:
+        Pp, Pm = P64.copy(), P64.copy()
+        Pp[i] += h
+        Pm[i] -= h
+        fd = (oracle.mlp_loss_grad(Pp, X64, T64, False) -
+              oracle.mlp_loss_grad(Pm, X64, T64, False)) / (2 * h)
+        assert grad[i] == pytest.approx(fd, rel=1e-4, abs=1e-6 * np.abs(G).max()), i
+
+
+def test_adam_update_matches_oracle(pk):
+    say("adam update")
+    P = random_params(5)
+    g = np.random.default_rng(6)
+    X = g.normal(0, 1, (40, 12)).astype(np.float32)
+    T = g.normal(0, 1, (40, 2)).astype(np.float32)
+    Pd, am, av = f32(P), torch.zeros(NP, device="cuda"), torch.zeros(NP, device="cuda")
+    lr = 1e-3
+    P64 = P.astype(np.float64)
+    m = np.zeros(NP)
+    v = np.zeros(NP)
+    for step in (1, 2):   # rows < batch: one update per epoch
+        _, G = oracle.mlp_loss_grad(P64, X.astype(np.float64), T.astype(np.float64))
+        P64, m, v = oracle.adam_step(P64, m, v, G, lr, step)
+        pk.mlp_train(Pd, am, av, f32(X), f32(T), 1, lr=lr, batch=64, step0=step - 1)
+        got = Pd.cpu().numpy().astype(np.float64)
+        big = np.abs(G) > 1e-3 * np.abs(G).max()   # where the update's sign is well defined
+        assert np.all(np.abs(got - P64)[big] <= 1e-6 + 1e-3 * lr), step
+        assert np.allclose(am.cpu().numpy(), m, rtol=1e-4, atol=1e-7 * np.abs(m).max())
+        P64 = got                                  # continue from the device parameters
+
+
+def test_training_reduces_loss_deterministically(pk):
+    say("training")
+    from paper_0907_4631_amd import proposer as PR
+    teacher = random_params(7, 0.4)
+    X = np.random.default_rng(8).normal(0, 1, (500, 12)).astype(np.float32)
+    T = oracle.mlp_forward(teacher.astype(np.float64), X.astype(np.float64)).astype(np.float32)
+    runs = []
+    for _ in range(2):
+        P, hist = PR.train(f32(X), f32(T), epochs=300, lr=3e-3, seed=3)
+        runs.append(P.cpu().numpy())
+    assert hist["train"][-1] < 0.1 * hist["train"][0]
+    assert hist["val"][-1][1] < 0.2 * hist["train"][0]
+    assert np.array_equal(runs[0], runs[1])
+
+
+def traced_solve(pk, A, b, t, tol, cap=64, **kw):
+    Ad = pk.DeviceCSR(A)
+    bd = torch.as_tensor(np.ascontiguousarray(b.T), device="cuda")
+    u = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+    s = pk.Solver(Ad, b.shape[1] - 1, tol=tol, **kw)
+    trace = pk.alloc_trace(cap)
+    s.opts.trace = trace.data_ptr()
+    s.opts.trace_cap = cap
+    st = s(t, bd, u)
+    return trace, st, u.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["lap2d", "convdiff"])
+def test_trace_records_and_labels_match_oracle(pk, kind):
+    say("trace and labels", kind)
+    from paper_0907_4631_amd import proposer as PR
+    A = W.laplace2d(40) if kind == "lap2d" else W.convdiff2d(40, 30.0, 30.0)
+    b = np.random.default_rng(9).standard_normal((A.shape[0], 2))
+    t, tol = 5e-3, 1e-8
+    trace, st, u = traced_solve(pk, A, b, t, tol, m_max=40)
+    ref, _ = oracle.phipm(t, A, b, tol=tol)
+    assert np.linalg.norm(u - ref) <= 10 * tol * max(1.0, np.linalg.norm(ref))
+    k = st["trace_len"]
+    assert k == st["steps"] and k >= 2
+    recs = pk.trace_records(trace, k)
+    assert sum(r.tau for r in recs) == pytest.approx(t, rel=1e-12)
+    assert all(r.t < s.t for r, s in zip(recs, recs[1:]))
+    assert all(r.m_have == 40 and r.m_use <= r.m_have for r in recs)
+    assert all(np.all(np.isfinite(np.frombuffer(r.features, dtype=np.float32))) for r in recs)
+    costs = PR.measure_costs()
+    for use_costs in (False, True):
+        X, T = pk.label_steps(trace, k, costs if use_costs else None)
+        X, T = X.cpu().numpy(), T.cpu().numpy()
+        oc = None
+        if use_costs:
+            oc = oracle.label_costs(costs.sync_s, costs.sync1_s, costs.bw_bytes_per_s,
+                                    costs.wg_bytes_per_s, costs.workgroups, list(costs.expm_s))
+        for q, r in enumerate(recs):
+            H = np.frombuffer(r.H, dtype=np.float64).reshape(pk.M_CAP + 1, pk.M_CAP)
+            ts, ms = oracle.label_step(H[:r.m_have + 1], r.m_use, r.m_have, r.p, r.lanczos, r.n,
+                                       r.nnz, r.t, r.tau, r.beta, r.t_end, r.tol, oc)
+            assert np.array_equal(X[q], np.frombuffer(r.features, dtype=np.float32))
+            m_gpu = int(round(T[q, 1] * 32))
+            tau_gpu = 10.0 ** float(T[q, 0]) / r.anorm
+            if m_gpu == ms:
+                assert tau_gpu == pytest.approx(ts, rel=2e-3), (q, use_costs)
+            else:   # a near tie between two dimensions: both costs must agree closely
+                def cost(mm, tt):
+                    kn = oracle.step_omega(H[:r.m_have + 1], mm, r.p, r.beta, tt, r.t_end,
+                                           r.tol)[1]
+                    w = (oracle.step_time(mm, r.p, r.lanczos, r.n, r.nnz, oc) if oc else
+                         oracle.cost_C1(r.lanczos, mm, r.p, r.nnz, r.n, oracle.cost_M(kn)))
+                    return w / tt
+                assert cost(m_gpu, tau_gpu) <= cost(ms, ts) * (1 + 5e-3), (q, m_gpu, ms)
+
+
+def test_proposer_keeps_error_control_and_warm_start(pk):
+    """Any proposer, even an untrained one, only seeds the steps: the result
+    still meets the tolerance.  The history buffer warm-starts the next call."""
+    say("proposer error control")
+    A = W.convdiff2d(64, 40.0, 40.0)
+    b = np.random.default_rng(10).standard_normal((A.shape[0], 3))
+    t, tol = 4e-3, 1e-8
+    ref, _ = oracle.phipm(t, A, b, tol=tol)
+    Ad = pk.DeviceCSR(A)
+    bd = torch.as_tensor(np.ascontiguousarray(b.T), device="cuda")
+    for seed in (11, 12):
+        P = f32(random_params(seed, 1.0))
+        u = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+        s = pk.Solver(Ad, 2, tol=tol)
+        s.opts.proposer = P.data_ptr()
+        st = s(t, bd, u)
+        assert st["status"] == 0 and st["proposals"] == st["steps"]
+        assert np.linalg.norm(u.cpu().numpy() - ref) <= 10 * tol * max(1, np.linalg.norm(ref))
+    hist = torch.zeros(4, dtype=torch.float64, device="cuda")
+    s = pk.Solver(Ad, 2, tol=tol)
+    s.opts.history = hist.data_ptr()
+    u = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+    st1 = s(t, bd, u)
+    h = hist.cpu().numpy()
+    assert h[3] == 1.0 and h[0] > 0 and h[1] >= 1
+    st2 = s(t, bd, u)
+    assert st2["rejected"] < st1["rejected"]
+    assert np.linalg.norm(u.cpu().numpy() - ref) <= 10 * tol * max(1, np.linalg.norm(ref))
+
+
+def test_trained_proposer_gains_on_held_out_problems(pk):
+    """The committed network (trained on the GPU by the pipeline in
+    paper_0907_4631_amd.proposer) against the plain step control on held-out
+    problems of the training families: fewer steps, fewer rejected attempts
+    and fewer products at the same accuracy.  Wall time is reported, not
+    asserted: on these problems the larger Krylov dimensions it chooses cost
+    about as much time as the steps they save."""
+    say("trained proposer gain")
+    from paper_0907_4631_amd import proposer as PR
+    P = PR.load()
+    probs = PR.training_problems(24, seed=7777)
+    tot = {"plain": np.zeros(4), "learned": np.zeros(4)}
+    for name, A, b, t, tol in probs:
+        Ad = pk.DeviceCSR(A)
+        bd = torch.as_tensor(np.ascontiguousarray(b.T), device="cuda")
+        outs = {}
+        for variant in ("plain", "learned"):
+            u = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+            s = pk.Solver(Ad, b.shape[1] - 1, tol=tol)
+            if variant == "learned":
+                s.opts.proposer = P.data_ptr()
+            st = s(t, bd, u)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s(t, bd, u, stats=False)
+            e1.record()
+            torch.cuda.synchronize()
+            tot[variant] += [st["steps"], st["rejected"], st["matvecs"], e0.elapsed_time(e1)]
+            outs[variant] = u.cpu().numpy()
+        ref = outs["plain"]
+        assert np.linalg.norm(outs["learned"] - ref) <= 10 * tol * max(1.0, np.linalg.norm(ref)), name
+    say("  totals [steps, rejected, matvecs, ms]: plain", tot["plain"], "learned", tot["learned"])
+    assert tot["learned"][0] <= 0.75 * tot["plain"][0]
+    assert tot["learned"][1] <= 0.6 * tot["plain"][1]
+    assert tot["learned"][2] <= tot["plain"][2]
