@@ -677,7 +677,7 @@ int phipm_plan_create(int count, const phipm_csr* A, const int32_t* p, const dou
   pl->wl = work_layout(nmax, nnzmax, pmax, std::min(o->m_max, nmax), pl->fp32);
   pl->team_ws = pl->wl.total;
   pl->nflags = (size_t)FLAG_STRIDE * 3 * (size_t)G;
-  pl->npart = (size_t)KMAX * 3 * (size_t)G;
+  pl->npart = (size_t)KMAX * 4 * (size_t)G;  // >= sum over teams of team_partials(size) + KMAX
   const size_t npart = pl->npart;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o2 = off; off = align256(off + bytes); return o2; };

@@ -70,25 +70,17 @@ __global__ __launch_bounds__(BLOCK) void k_krylov(Problem P, Work<double> w, con
   block_reduce<1>(a1, RED_SUM, sh.blk);
   if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return;
   const double beta = sqrt(sh.red[0]);
-  int have = 0;
-  double h = beta;
-  while (have < m) {
-    if (have == 0)
-      h = krylov_step<double, double>(tm, P, w, P.val, 1.0, lanczos != 0, 0, v, 1.0 / beta, rb,
-                                      re, sh);
-    else
-      h = krylov_step<double, double>(tm, P, w, P.val, 1.0, lanczos != 0, have,
-                                      (have - 1) & 1 ? w.y1 : w.y0, 1.0 / h, rb, re, sh);
-    if (h < 0.0) return;
-    ++have;
-    if (h == 0.0) break;
+  KrylovCtl kc{0, 1, 0, 1};
+  while (!kc.broke && kc.have < m && kc.have < P.n) {
+    const bool ok = kc.have == 0
+                        ? krylov_iter<double, double>(tm, P, w, P.val, 1.0, lanczos != 0, 0.0, kc,
+                                                      v, 1.0 / beta, rb, re, sh)
+                        : krylov_iter<double, double>(tm, P, w, P.val, 1.0, lanczos != 0, 0.0, kc,
+                                                      nullptr, 0.0, rb, re, sh);
+    if (!ok) return;
   }
-  if (h > 0.0) {
-    const double* ys = (have - 1) & 1 ? w.y1 : w.y0;
-    const double sc = 1.0 / h;
-    double* vh = w.V + (long long)have * w.ldv;
-    for (int r = rb + threadIdx.x; r < re; r += BLOCK) vh[r] = ys[r] * sc;
-  }
+  if (!krylov_finalize<double>(tm, P, w, lanczos != 0, 0.0, kc, rb, re, sh)) return;
+  const int have = kc.have;
   if (tm.rank == 0) {
     for (int e = threadIdx.x; e < (m + 1) * m; e += BLOCK) {
       const int i = e / m, j = e - i * m;

@@ -132,6 +132,7 @@ struct Shared {
   double blk[KMAX];
   double red[KMAX];
   double h1[KMAX];
+  double qv[KMAX];
   double coef[P_MAX + 1];
   double yb[M_CAP + 2];
 };
@@ -163,113 +164,320 @@ __device__ __forceinline__ SpmvSmem<double>& smem_for<double>(Shared& sh) { retu
 template <>
 __device__ __forceinline__ SpmvSmem<float>& smem_for<float>(Shared& sh) { return sh.sm32; }
 
-// blk[k] = sum over own rows of V[:, i0+k] . y for k < K (block-reduced, float64).
-// Columns are taken 8 at a time; each wave reduces its partial sums with DPP
-// and parks them in LDS, and the waves' sums are added in wave order after a
-// single barrier.
+// Block sums over own rows (float64): blk[k] = V[:, i0+k] . w for k < K,
+// and when with_u also blk[K+k] = V[:, i0+k] . u, blk[2K] = u . u,
+// blk[2K+1] = u . w.  Jobs are the K basis columns and one (u.u, u.w) job.
+// Each job gets the largest power-of-two share of the 16 wavefronts (at
+// least one; with more jobs than wavefronts they go round robin), and a
+// wavefront streams its share of the workgroup's rows of that column in
+// 64-row chunks, so many independent loads are in flight; u and w are
+// re-read from L1.  Partial sums are reduced with DPP and then across a
+// job's wavefronts in a fixed order.
 template <typename T>
-__device__ __forceinline__ void phase_dots(const T* V, long long ldv, int i0, int K, const T* y,
-                                           int rb, int re, Shared& sh) {
+__device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, int K, const T* U,
+                                            const T* Wv, bool with_u, int rb, int re,
+                                            Shared& sh) {
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-  for (int g = 0; g < K; g += 8) {
-    double a[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] = 0.0;
-    const int kk = K - g < 8 ? K - g : 8;
-    for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
-      const double yr = (double)y[r];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < kk) a[q] += (double)V[(long long)(i0 + g + q) * ldv + r] * yr;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      if (q < kk) {
-        const double t = wave_sum((double)a[q]);
-        if (lane == 0) sh.wpart[wv][g + q] = t;
+  const int jobs = K + 1;
+  int wpj = 1;
+  while (2 * wpj * jobs <= NWAVES) wpj *= 2;
+  const int seg = wv % wpj;
+  // the rows of u and w were written by other threads of the workgroup
+  __syncthreads();
+  for (int job = wv / wpj; job < jobs; job += NWAVES / wpj) {
+    double s0 = 0.0, s1 = 0.0;
+    if (job < K) {
+      const T* col = V + (long long)(i0 + job) * ldv;
+#pragma unroll 4
+      for (int r = rb + seg * WAVE + lane; r < re; r += WAVE * wpj) {
+        const double v = (double)col[r];
+        s0 += v * (double)Wv[r];
+        if (with_u) s1 += v * (double)U[r];
       }
+    } else {
+#pragma unroll 4
+      for (int r = rb + seg * WAVE + lane; r < re; r += WAVE * wpj) {
+        const double ur = (double)U[r];
+        s0 += ur * ur;
+        s1 += ur * (double)Wv[r];
+      }
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) {
+      sh.wpart[seg][2 * job] = s0;
+      sh.wpart[seg][2 * job + 1] = s1;
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < K; k += BLOCK) {
-    double t = sh.wpart[0][k];
-    for (int w2 = 1; w2 < NWAVES; ++w2) t += sh.wpart[w2][k];
-    sh.blk[k] = t;
+  for (int job = threadIdx.x; job < jobs; job += BLOCK) {
+    double s0 = sh.wpart[0][2 * job], s1 = sh.wpart[0][2 * job + 1];
+    for (int q = 1; q < wpj; ++q) {
+      s0 += sh.wpart[q][2 * job];
+      s1 += sh.wpart[q][2 * job + 1];
+    }
+    if (job < K) {
+      sh.blk[job] = s0;
+      sh.blk[K + job] = s1;
+    } else {
+      sh.blk[2 * K] = s0;
+      sh.blk[2 * K + 1] = s1;
+    }
   }
   __syncthreads();
 }
 
-// y -= V[:, i0..i0+K) h over own rows.
+// Team-uniform state of an incremental Krylov build.  Columns 0..have-1 of
+// V are final; U holds the candidate for column `have` (orthogonalised once,
+// not normalised) unless u_final, when it holds v_have itself.  Columns
+// 0..have-2 of H are final, column have-1 holds its first-pass
+// coefficients until finalised.
+struct KrylovCtl {
+  int have, u_final, broke, final_col;  // final_col: H column have-1 is final
+};
+
+// Second pass of the candidate in U against columns [zb, j) of V and its
+// norm.  The coefficients s go to sh.h1[0..K) and, for rank 0, into column
+// j-1 of H with H[j][j-1] = beta.  beta comes from Pythagoras,
+// beta^2 = u.u - |s|^2, unless the first pass left more than a quarter of
+// ||u||^2 in span(V) (cancellation), when U is reorthogonalised in place
+// and its norm reduced directly (one more team barrier; then sh.h1 is the
+// applied correction and *applied is set).  Returns beta, or -1 on abort.
 template <typename T>
-__device__ __forceinline__ void phase_project(const T* V, long long ldv, int i0, int K, const double* h, T* y,
-                              int rb, int re) {
-  for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
-    double yr = (double)y[r];
-    for (int k = 0; k < K; ++k) yr -= h[k] * (double)V[(long long)(i0 + k) * ldv + r];
-    y[r] = T(yr);
-  }
-}
-
-// One step j of the Krylov process (Arnoldi with CGS2, or Lanczos with CGS2
-// against the two previous vectors).  src/scale define v_j = T(src*scale):
-// v_j is written to V[:, j] for own rows and gathered for the product.
-// Returns h_{j+1,j}, or a negative value if the team was aborted.
-template <typename T, typename S>
-__device__ __forceinline__ double krylov_step(const Team& tm, const Problem& P, const Work<T>& w, const T* valT,
-                              double sgn, bool lanczos, int j, const S* src, S scale, int rb,
-                              int re, Shared& sh) {
-  T* y = (j & 1) ? w.y1 : w.y0;
-  T* vj = w.V + (long long)j * w.ldv;
-  auto vload = [&](int c) -> T { return T(src[c] * scale); };
-  // values and basis are stored as T; products and sums are formed in FP64
-  // (a float times a float is exact in double), so the FP32 basis does not
-  // lose digits to the cancellation inside stiff stencil rows
-  auto vload64 = [&](int c) -> double { return (double)vload(c); };
-  // P1: y = A v_j
-  for (int r0 = rb; r0 < re; r0 += BLOCK) {
-    const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
-    const double acc = spmv_tile<T, double>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), vload64);
-    const int r = r0 + threadIdx.x;
-    if (r < r1) {
-      y[r] = T(sgn * acc);
-      vj[r] = vload(r);
-    }
-  }
-  const int i0 = lanczos ? (j > 0 ? j - 1 : 0) : 0;
-  const int K = j - i0 + 1;
-  phase_dots<T>(w.V, w.ldv, i0, K, y, rb, re, sh);
-  if (!team_sync(tm, sh.blk, K, RED_SUM, sh.red)) return -1.0;
-  // P2: first projection, then the second pass of dot products
-  for (int k = threadIdx.x; k < K; k += BLOCK) sh.h1[k] = sh.red[k];
-  phase_project<T>(w.V, w.ldv, i0, K, sh.red, y, rb, re);
-  phase_dots<T>(w.V, w.ldv, i0, K, y, rb, re, sh);
-  if (!team_sync(tm, sh.blk, K, RED_SUM, sh.red)) return -1.0;
-  // P3: second projection and the norm
-  phase_project<T>(w.V, w.ldv, i0, K, sh.red, y, rb, re);
-  {
-    double acc[1];
-    double a = 0.0;
-    for (int r = rb + threadIdx.x; r < re; r += BLOCK) a += (double)y[r] * (double)y[r];
-    acc[0] = a;
-    if (tm.rank == 0) {
-      // workgroup 0 records column j of H (it alone reads H)
-      for (int i = threadIdx.x; i <= M_CAP; i += BLOCK) {
-        double hv = 0.0;
-        if (i >= i0 && i <= j) hv = sh.h1[i - i0] + sh.red[i - i0];
-        w.H[(long long)i * M_CAP + j] = hv;
-      }
+__device__ __forceinline__ double second_pass(const Team& tm, const Work<T>& w, int zb, int j,
+                                              double a, T* U, int rb, int re, bool* applied,
+                                              Shared& sh) {
+  const int K = j - zb;
+  double ss = 0.0;
+  for (int k = 0; k < K; ++k) ss += sh.h1[k] * sh.h1[k];
+  double b2 = a - ss;
+  *applied = false;
+  if (!(ss <= 0.25 * a) || !(b2 > 0.0)) {
+    double acc[1] = {0.0};
+    for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
+      double ur = (double)U[r];
+      for (int k = 0; k < K; ++k) ur -= sh.h1[k] * (double)w.V[(long long)(zb + k) * w.ldv + r];
+      const T ut = T(ur);
+      U[r] = ut;
+      acc[0] += (double)ut * (double)ut;
     }
     block_reduce<1>(acc, RED_SUM, sh.blk);
+    if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.qv)) return -1.0;
+    b2 = sh.qv[0];
+    *applied = true;
+    __syncthreads();  // sh.qv is reused by the caller
   }
-  if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return -1.0;
-  const double hn = sqrt(sh.red[0]);
-  if (tm.rank == 0 && threadIdx.x == 0) {
-    w.H[(long long)(j + 1) * M_CAP + j] = hn;
-    w.st->matvecs += 1;
-    // product, v_j store, and the K-column passes of P1 (K+1), P2 (2K+3), P3 (K+3)
-    w.st->bytes += spmv_bytes(P, sizeof(T)) + (4.0 * K + 8.0) * sizeof(T) * (double)P.n;
+  return sqrt(b2 > 0.0 ? b2 : 0.0);
+}
+
+// One iteration j of the Krylov process, classical Gram-Schmidt applied
+// twice with the second pass delayed by one iteration: the product w = A u_j
+// of the candidate u_j, then ONE team reduction of V^T w, V^T u_j, u_j.u_j
+// and u_j.w over the projection window, from which every workgroup derives
+// (identically) the second-pass coefficients s and norm beta of u_j, hence
+// v_j = (u_j - V s) / beta, column j-1 of H (first-pass + s, beta), and the
+// first-pass coefficients of A v_j = (w - A V s) / beta through the Arnoldi
+// relation A V s = V (H s) + beta s_{j-1} v_j.  A row-local pass then writes
+// v_j and the next candidate; a plain team barrier publishes it for the
+// next product.  In exact arithmetic V and H equal those of CGS2.
+// Arnoldi projects against all previous columns; Lanczos against the two
+// most recent ones (second pass of u_j over {j-2, j-1}, first pass of A v_j
+// over {j-1, j}).  With seed != null (j = 0) v_0 = seed * seed_scale is
+// gathered directly and stored.  Returns false if the team was aborted.
+template <typename T, typename S>
+__device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, const Work<T>& w,
+                                            const T* valT, double sgn, bool lanczos, double bd_tol,
+                                            KrylovCtl& kc, const S* seed, double seed_scale,
+                                            int rb, int re, Shared& sh) {
+  const int j = kc.have;
+  T* U = w.y0;
+  T* Wv = w.y1;
+  const bool uf = kc.u_final != 0;
+  // P1: w = A u_j
+  {
+    T* v0 = w.V;
+    for (int r0 = rb; r0 < re; r0 += BLOCK) {
+      const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
+      double acc;
+      if (seed) {
+        auto ld = [&](int c) -> double { return (double)T(seed[c] * seed_scale); };
+        acc = spmv_tile<T, double>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), ld);
+      } else {
+        auto ld = [&](int c) -> double { return (double)U[c]; };
+        acc = spmv_tile<T, double>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), ld);
+      }
+      const int r = r0 + threadIdx.x;
+      if (r < r1) {
+        Wv[r] = T(sgn * acc);
+        if (seed) {
+          const T v = T(seed[r] * seed_scale);
+          v0[r] = v;
+          U[r] = v;
+        }
+      }
+    }
   }
-  return hn;
+  // P2: one reduction over the window [zb, j)
+  const int zb = lanczos ? (j > 2 ? j - 2 : 0) : 0;
+  const int K = j - zb;
+  phase_dots2<T>(w.V, w.ldv, zb, K, U, Wv, !uf, rb, re, sh);
+  if (!team_sync(tm, sh.blk, 2 * K + 2, RED_SUM, sh.red)) return false;
+  const double a = sh.red[2 * K], c = sh.red[2 * K + 1];
+  // z -> sh.red[0..K), s -> sh.h1[0..K)
+  for (int k = threadIdx.x; k < K; k += BLOCK) sh.h1[k] = uf ? 0.0 : sh.red[K + k];
+  __syncthreads();
+  double beta = 1.0;
+  bool applied = false;
+  if (!uf) {
+    beta = second_pass<T>(tm, w, zb, j, a, U, rb, re, &applied, sh);
+    if (beta < 0.0) return false;
+  }
+  const double sj1 = (!uf && j > 0) ? sh.h1[K - 1] : 0.0;   // s_{j-1}
+  if (!uf && beta <= bd_tol) {
+    // invariant subspace: finalise column j-1; there is no v_j.  No
+    // workgroup reads H in this iteration, so workgroup 0 writes it now.
+    if (tm.rank == 0) {
+      for (int i = threadIdx.x; i < j; i += BLOCK)
+        if (i >= zb) w.H[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
+      if (threadIdx.x == 0) {
+        w.H[(long long)j * M_CAP + (j - 1)] = beta;
+        w.st->matvecs += 1;
+        w.st->bytes += spmv_bytes(P, sizeof(T)) + (K + 2.0) * sizeof(T) * (double)P.n;
+      }
+    }
+    __syncthreads();
+    kc.broke = 1;
+    kc.final_col = 1;
+    return true;
+  }
+  // g = H s over rows [ub, j) from the stored H (its column j-1 still holds
+  // the first pass: add s_i s_{j-1}); the coefficients of the row-local pass
+  //   v_j = (u - V s) / beta
+  //   u_{j+1} = w / beta - V q - (s_{j-1} + h_jj) v_j,  q = g / beta + h1
+  // with h1 the first-pass coefficients of A v_j on the window.
+  const int ub = lanczos ? (j > 3 ? j - 3 : 0) : 0;
+  const int KU = j - ub;
+  double sdz = 0.0;
+  for (int k = 0; k < K; ++k) sdz += sh.h1[k] * sh.red[k];
+  const double ib = 1.0 / beta;
+  const double hjj = uf ? c : (c - sdz) * ib * ib - sj1;   // first pass, row j of column j
+  {
+    // one wavefront per row of g, lanes across the columns of H (a row of H
+    // is contiguous), so the reads of H are issued together
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    for (int i = wv; i < KU; i += NWAVES) {
+      const int row = ub + i;
+      double g = 0.0;
+      if (!uf) {
+        for (int k = lane; k < K; k += WAVE) {
+          const int col = zb + k;
+          if (row <= col + 1) g += w.H[(long long)row * M_CAP + col] * sh.h1[k];
+        }
+        g = wave_sum(g);
+        if (row >= zb) g += sh.h1[row - zb] * sj1;
+      }
+      if (lane == 0) {
+        const bool inwin = !lanczos || row == j - 1;
+        const double z = row >= zb ? sh.red[row - zb] : 0.0;
+        const double h1 = inwin ? (z - g) * ib : 0.0;
+        sh.qv[i] = g * ib + h1;
+        sh.blk[i] = h1;                                                     // column j of H
+        sh.wpart[0][i] = (!applied && row >= zb) ? sh.h1[row - zb] : 0.0;  // s on [ub, j)
+      }
+    }
+  }
+  __syncthreads();
+  // P3: row-local pass, then publish u_{j+1}
+  const double tj = sj1 + hjj;
+  T* vj = w.V + (long long)j * w.ldv;
+  for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
+    double vs = 0.0, vq = 0.0;
+    for (int i = 0; i < KU; ++i) {
+      const double v = (double)w.V[(long long)(ub + i) * w.ldv + r];
+      vs += sh.wpart[0][i] * v;
+      vq += sh.qv[i] * v;
+    }
+    const double ur = (double)U[r];
+    const T vjt = uf ? T(ur) : T((ur - vs) * ib);
+    if (!uf) vj[r] = vjt;
+    U[r] = T((double)Wv[r] * ib - vq - tj * (double)vjt);
+  }
+  if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return false;
+  if (tm.rank == 0) {
+    // every workgroup has read H for g: column j-1 final, column j first
+    // pass (rows outside the window zeroed)
+    for (int i = threadIdx.x; i <= M_CAP; i += BLOCK) {
+      if (!uf && j > 0 && i < j && i >= zb) w.H[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
+      double hv = 0.0;
+      if (i >= ub && i < j) hv = sh.blk[i - ub];
+      else if (i == j) hv = hjj;
+      w.H[(long long)i * M_CAP + j] = hv;
+    }
+    if (threadIdx.x == 0) {
+      if (!uf && j > 0) w.H[(long long)j * M_CAP + (j - 1)] = beta;
+      w.st->matvecs += 1;
+      // product (+ the v_0 store), the fused dots (K columns, u, w), the
+      // row-local pass (KU columns, u, w read; v_j, u written)
+      w.st->bytes += spmv_bytes(P, sizeof(T)) + (seed ? 2.0 : 0.0) * sizeof(T) * (double)P.n +
+                     (K + 2.0 + KU + 2.0 + (uf ? 1.0 : 2.0)) * sizeof(T) * (double)P.n;
+    }
+    __syncthreads();
+  }
+  kc.have = j + 1;
+  kc.u_final = 0;
+  kc.final_col = 0;
+  return true;
+}
+
+// Finalise column have-1: second pass and norm of the candidate in U, then
+// v_have into V[:, have] and U (the corrector's vector, and the start of
+// any later extension).  Returns false if the team was aborted.
+template <typename T>
+__device__ __forceinline__ bool krylov_finalize(const Team& tm, const Problem& P,
+                                                const Work<T>& w, bool lanczos, double bd_tol,
+                                                KrylovCtl& kc, int rb, int re, Shared& sh) {
+  if (kc.broke || kc.u_final || kc.have == 0) return true;
+  const int j = kc.have;
+  T* U = w.y0;
+  const int zb = lanczos ? (j > 2 ? j - 2 : 0) : 0;
+  const int K = j - zb;
+  phase_dots2<T>(w.V, w.ldv, zb, K, U, U, true, rb, re, sh);
+  if (!team_sync(tm, sh.blk + K, K + 1, RED_SUM, sh.red)) return false;
+  // sh.red[0..K) = V^T u, sh.red[K] = u.u
+  const double a = sh.red[K];
+  for (int k = threadIdx.x; k < K; k += BLOCK) sh.h1[k] = sh.red[k];
+  __syncthreads();
+  bool applied = false;
+  const double beta = second_pass<T>(tm, w, zb, j, a, U, rb, re, &applied, sh);
+  if (beta < 0.0) return false;
+  if (tm.rank == 0) {
+    for (int i = threadIdx.x; i < j; i += BLOCK)
+      if (i >= zb) w.H[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
+    if (threadIdx.x == 0) {
+      w.H[(long long)j * M_CAP + (j - 1)] = beta;
+      w.st->bytes += (K + 1.0) * sizeof(T) * (double)P.n;
+    }
+  }
+  kc.final_col = 1;
+  if (beta <= bd_tol) {
+    __syncthreads();
+    kc.broke = 1;
+    return true;
+  }
+  const double ib = 1.0 / beta;
+  T* vh = w.V + (long long)j * w.ldv;
+  for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
+    double ur = (double)U[r];
+    if (!applied)
+      for (int k = 0; k < K; ++k) ur -= sh.h1[k] * (double)w.V[(long long)(zb + k) * w.ldv + r];
+    const T v = T(ur * ib);
+    vh[r] = v;
+    U[r] = v;
+  }
+  if (tm.rank == 0 && threadIdx.x == 0) w.st->bytes += (K + 3.0) * sizeof(T) * (double)P.n;
+  __syncthreads();
+  kc.u_final = 1;
+  return true;
 }
 
 enum { SOLVE_DONE = 0, SOLVE_ABORTED = -1, SOLVE_NEEDS_FP64 = 1 };
@@ -780,33 +988,28 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       const double* wp = p == 0 ? P.u : w.W + (long long)(p - 1) * w.ldw;
 
       // ---- attempts of this step (Algorithm 3 inner loop)
-      int have = 0;
-      bool broke = false;
-      double hprev = beta;
+      KrylovCtl kc{0, 1, 0, 1};  // v_0 = w_p / beta is final by construction
+      const double bd_tol = st->bd_tol;
+      // build (or extend) the basis to `target` columns and finalise the last
+      auto build = [&](int target) -> bool {
+        while (!kc.broke && kc.have < target && kc.have < n) {
+          const bool ok =
+              kc.have == 0
+                  ? krylov_iter<T, double>(tm, P, w, valT, sgn, lanczos, bd_tol, kc, wp, 1.0 / beta,
+                                           rb, re, sh)
+                  : krylov_iter<T, double>(tm, P, w, valT, sgn, lanczos, bd_tol, kc, nullptr, 0.0,
+                                           rb, re, sh);
+          if (!ok) return false;
+        }
+        if (!krylov_finalize<T>(tm, P, w, lanczos, bd_tol, kc, rb, re, sh)) return false;
+        if (kc.have >= n) kc.broke = 1;  // the whole space: exact for any tau
+        return true;
+      };
       for (;;) {
         const int m = st->m;
-        if (beta > 0.0) {
-          while (!broke && have < m) {
-            double h;
-            if (have == 0)
-              h = krylov_step<T, double>(tm, P, w, valT, sgn, lanczos, 0, wp, 1.0 / beta, rb, re, sh);
-            else
-              h = krylov_step<T, T>(tm, P, w, valT, sgn, lanczos, have,
-                                    (have - 1) & 1 ? w.y1 : w.y0, T(1.0 / hprev), rb, re, sh);
-            if (h < 0.0) return SOLVE_ABORTED;  // aborted
-            ++have;
-            hprev = h;
-            if (h <= st->bd_tol || have == n) broke = true;
-          }
-          if (!broke) {
-            // v_have for the corrector (row-local)
-            const T* ys = (have - 1) & 1 ? w.y1 : w.y0;
-            const T sc = T(1.0 / hprev);
-            T* vh = w.V + (long long)have * w.ldv;
-            for (int r = rb + tid; r < re; r += BLOCK) vh[r] = T(ys[r] * sc);
-            if (tm.rank == 0 && tid == 0) st->bytes += 2.0 * sizeof(T) * n;
-          }
-        }
+        if (beta > 0.0 && !build(m)) return SOLVE_ABORTED;
+        const int have = kc.have;
+        const bool broke = kc.broke != 0;
         if (tm.rank == 0) {
           DecideArgs da{P.tol, P.tau_fixed, (double)P.nnz, (double)n, P.max_attempts,
                         p, P.adapt_m, P.corrector, have, broke ? 1 : 0, fp32 ? 1 : 0,
@@ -846,27 +1049,17 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
           // training record: extend the basis (prefix-stable, tau-independent)
           // to m_cap columns so that hindsight labels can weigh every m,
           // then store H
-          if (!broke) {
-            const int m_ext = st->m_cap;
-            while (!broke && have < m_ext) {
-              const double h = krylov_step<T, T>(tm, P, w, valT, sgn, lanczos, have,
-                                                 (have - 1) & 1 ? w.y1 : w.y0, T(1.0 / hprev),
-                                                 rb, re, sh);
-              if (h < 0.0) return SOLVE_ABORTED;
-              ++have;
-              hprev = h;
-              if (h <= st->bd_tol || have == n) broke = true;
-            }
-          }
+          if (!kc.broke && !build(st->m_cap)) return SOLVE_ABORTED;
+          const int mh = kc.have;
           if (tm.rank == 0) {
             const int slot = st->trace_len;
             if (slot < P.trace_cap) {
               double* dst = P.trace[slot].H;
-              for (int e = tid; e < (have + 1) * M_CAP; e += BLOCK) {
+              for (int e = tid; e < (mh + 1) * M_CAP; e += BLOCK) {
                 const int jj = e % M_CAP;
-                dst[e] = jj < have ? w.H[e] : 0.0;
+                dst[e] = jj < mh ? w.H[e] : 0.0;
               }
-              if (tid == 0) P.trace[slot].m_have = have;
+              if (tid == 0) P.trace[slot].m_have = mh;
             }
             __syncthreads();
             if (tid == 0) st->trace_len = slot + 1;

@@ -13,7 +13,7 @@ constexpr int WAVE = 64;                 // CDNA wavefront
 constexpr int NWAVES = BLOCK / WAVE;
 constexpr int M_CAP = 128;               // largest Krylov dimension
 constexpr int P_MAX = 8;                 // largest p
-constexpr int KMAX = M_CAP + 8;          // widest team reduction
+constexpr int KMAX = 2 * M_CAP + 8;      // widest team reduction
 constexpr int NMAX_EXPM = M_CAP + P_MAX + 1;
 
 constexpr int TEAM_GROUP = 16;            // workgroups per arrival group
@@ -42,7 +42,7 @@ struct Team {
   unsigned* abort;     // abort flag shared by every team of the launch
   unsigned* garr;      // group leaders' epochs, FLAG_STRIDE apart
   unsigned* arr;       // members' epochs, FLAG_STRIDE apart
-  double* partials;    // [KMAX][size] per-workgroup values, then [KMAX][groups] group sums
+  double* partials;    // [size][KMAX] per-workgroup values, then 2 x [groups][KMAX] group sums
   double* result;      // [KMAX]
   uint64_t spin_ticks; // wall-clock budget of one wait
 };
@@ -72,7 +72,7 @@ __device__ __forceinline__ Team make_team(int rank, int size, unsigned* flags, u
 
 // Partials a team needs (doubles).
 __host__ __device__ inline size_t team_partials(int size) {
-  return (size_t)KMAX * (size + (size + TEAM_GROUP - 1) / TEAM_GROUP);
+  return (size_t)KMAX * (size + 2 * ((size + TEAM_GROUP - 1) / TEAM_GROUP));
 }
 
 enum RedOp { RED_SUM = 0, RED_MAX = 1 };
@@ -173,40 +173,61 @@ __device__ __forceinline__ void reduce_rows(const double* src, int ld, int cnt, 
   }
 }
 
-// Wave 0 of the calling workgroup waits until flags[base .. base+cnt) (cnt <=
-// 64, one per lane, FLAG_STRIDE apart) have all reached epoch e.  Returns 0
-// if the team was aborted or the wait ran out of time (then sets abort).
-__device__ __forceinline__ int wait_flags(const Team& tm, unsigned* flags, int cnt, unsigned e) {
-  const int lane = threadIdx.x % WAVE;
-  const uint64_t t0 = wall_clock64();
-  int ok = 1;
-  int all = 0;
-  while (ok && !all) {
-    const unsigned f = lane < cnt ? ld_relaxed(flags + (size_t)lane * FLAG_STRIDE) : e;
-    all = __all((int)(f - e) >= 0);
-    if (!all) {
-      __builtin_amdgcn_s_sleep(1);
-      if (ld_relaxed(tm.abort)) ok = 0;
-      else if (wall_clock64() - t0 > tm.spin_ticks) {
-        st_relaxed(tm.abort, 1u);
-        ok = 0;
+// Waves 0..ceil(cnt/64)-1 of the calling workgroup wait until the cnt flags
+// at flags, FLAG_STRIDE apart (one per lane), have all reached epoch e; the
+// workgroup then takes an agent-scope acquire.  Returns false (in every
+// thread) if the team was aborted or a wait ran out of time (then it sets
+// abort).
+__device__ __forceinline__ bool wait_flags(const Team& tm, const unsigned* flags, int cnt,
+                                           unsigned e) {
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  if (wv * WAVE < cnt) {
+    const int i = wv * WAVE + lane;
+    const uint64_t t0 = wall_clock64();
+    int all = 0, bad = 0;
+    while (!all && !bad) {
+      const unsigned f = i < cnt ? ld_relaxed(const_cast<unsigned*>(flags) + (size_t)i * FLAG_STRIDE)
+                                 : e;
+      all = __all((int)(f - e) >= 0);
+      if (!all) {
+        __builtin_amdgcn_s_sleep(1);
+        if (ld_relaxed(tm.abort)) bad = 1;
+        else if (wall_clock64() - t0 > tm.spin_ticks) {
+          st_relaxed(tm.abort, 1u);
+          bad = 1;
+        }
       }
     }
+    if (bad && lane == 0) s_bad = 1;
   }
-  return ok;
+  __syncthreads();
+  if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return s_bad == 0;
 }
 
-// Synchronise the team and reduce K per-workgroup values.  blk (shared memory)
-// holds this workgroup's K values; on return out (shared memory) holds the
-// team-wide reduction, identical in every workgroup.  K = 0 is a plain
-// barrier.  Group leaders sum their group's values in rank order and
-// workgroup 0 sums the group sums in group order, so the result does not
-// depend on timing.  Returns false if the team was aborted (a wait ran past
-// its time budget); callers then leave the kernel.
+// Synchronise the team and reduce K (<= KMAX) per-workgroup values.  blk
+// (shared memory) holds this workgroup's K values; on return out (shared
+// memory) holds the team-wide reduction, identical in every workgroup (sums
+// in a fixed order, so bitwise reproducible for a given team size).  K = 0
+// is a plain barrier.  Every workgroup writes its values contiguously and
+// posts its epoch in its own 128-byte flag line; there are no
+// read-modify-write atomics.
+//  * K <= 8 (and plain barriers): workgroup 0 polls every flag, reduces the
+//    values (one wave per value, lanes over workgroups) and publishes the
+//    generation word, which the others poll.
+//  * K > 8: the first workgroup of each group of TEAM_GROUP polls its members,
+//    reduces their values in rank order and posts a group flag; every
+//    workgroup then polls the group flags and reduces the group sums itself
+//    in group order (no further publication step).
+// Returns false if the team was aborted (a wait ran past its time budget);
+// callers then leave the kernel.
 __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int K, int op,
                                           double* out) {
   __shared__ unsigned s_epoch;
-  __shared__ int s_ok;
   const int tid = threadIdx.x;
   if (tm.size == 1) {
     __syncthreads();
@@ -214,74 +235,89 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
     __syncthreads();
     return true;
   }
+  const int PS = KMAX;
   const int ngroups = (tm.size + TEAM_GROUP - 1) / TEAM_GROUP;
-  const int grp = tm.rank / TEAM_GROUP;
-  const int g0 = grp * TEAM_GROUP;
-  const int gsz = tm.size - g0 < TEAM_GROUP ? tm.size - g0 : TEAM_GROUP;
-  const bool leader = tm.rank == g0;
-  double* gsum = tm.partials + (size_t)KMAX * tm.size;  // [KMAX][ngroups]
-  for (int k = tid; k < K; k += BLOCK) tm.partials[(size_t)k * tm.size + tm.rank] = blk[k];
+  unsigned* my = tm.arr + (size_t)tm.rank * FLAG_STRIDE;
+  for (int k = tid; k < K; k += BLOCK) tm.partials[(size_t)tm.rank * PS + k] = blk[k];
   __syncthreads();
   if (tid == 0) {
-    const unsigned e = ld_relaxed(tm.gen) + 1u;
+    const unsigned e = ld_relaxed(my) + 1u;  // this workgroup's own epoch count
     s_epoch = e;
-    s_ok = 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    st_relaxed(tm.arr + (size_t)tm.rank * FLAG_STRIDE, e);
+    st_relaxed(my, e);
   }
   __syncthreads();
   const unsigned e = s_epoch;
-  if (leader) {
-    if (tid < WAVE) {
-      const int ok = wait_flags(tm, tm.arr + (size_t)g0 * FLAG_STRIDE, gsz, e);
-      if (tid == 0) {
-        s_ok = ok;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      }
-    }
-    __syncthreads();
-    if (!s_ok) return false;
-    reduce_rows(tm.partials + g0, tm.size, gsz, K, op, gsum, ngroups, grp);
-    __syncthreads();
-    if (tid == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      st_relaxed(tm.garr + (size_t)grp * FLAG_STRIDE, e);
-    }
+  if (K <= 8) {
     if (tm.rank == 0) {
-      if (tid < WAVE) {
-        const int ok = wait_flags(tm, tm.garr, ngroups, e);
-        if (tid == 0) {
-          s_ok = ok;
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (!wait_flags(tm, tm.arr, tm.size, e)) return false;
+      const int lane = tid % WAVE, wv = tid / WAVE;
+      for (int k = wv; k < K; k += NWAVES) {
+        double a = (op == RED_SUM) ? 0.0 : -INFINITY;
+        for (int r = lane; r < tm.size; r += WAVE) {
+          const double v = tm.partials[(size_t)r * PS + k];
+          a = (op == RED_SUM) ? a + v : nanmax(a, v);
         }
+        a = (op == RED_SUM) ? wave_sum(a) : wave_max(a);
+        if (lane == 0) tm.result[k] = a;
       }
-      __syncthreads();
-      if (!s_ok) return false;
-      reduce_rows(gsum, ngroups, ngroups, K, op, tm.result, 1, 0);
       __syncthreads();
       if (tid == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         st_relaxed(tm.gen, e);
       }
+    } else {
+      if (!wait_flags(tm, tm.gen, 1, e)) return false;
+    }
+    for (int k = tid; k < K; k += BLOCK) out[k] = tm.result[k];
+    __syncthreads();
+    return true;
+  }
+  // group sums alternate between two buffers by epoch parity: a leader may
+  // write the next sync's sums while a slower workgroup of another group
+  // still reads this one's, but not two syncs ahead (it would need that
+  // workgroup's arrival)
+  double* gsum = tm.partials + ((size_t)tm.size + (size_t)(e & 1u) * ngroups) * PS;
+  const int grp = tm.rank / TEAM_GROUP;
+  const int g0 = grp * TEAM_GROUP;
+  const int gsz = tm.size - g0 < TEAM_GROUP ? tm.size - g0 : TEAM_GROUP;
+  if (tm.rank == g0) {
+    if (!wait_flags(tm, tm.arr + (size_t)g0 * FLAG_STRIDE, gsz, e)) return false;
+    for (int k = tid; k < K; k += BLOCK) {
+      double v[TEAM_GROUP];
+#pragma unroll
+      for (int r = 0; r < TEAM_GROUP; ++r)
+        v[r] = r < gsz ? tm.partials[(size_t)(g0 + r) * PS + k] : v[0];
+      double a = v[0];
+#pragma unroll
+      for (int r = 1; r < TEAM_GROUP; ++r)
+        if (r < gsz) a = (op == RED_SUM) ? a + v[r] : nanmax(a, v[r]);
+      gsum[(size_t)grp * PS + k] = a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      st_relaxed(tm.garr + (size_t)grp * FLAG_STRIDE, e);
     }
   }
-  if (tm.rank != 0 && tid == 0) {
-    const uint64_t t0 = wall_clock64();
-    int ok = 1;
-    while (ok && (int)(ld_relaxed(tm.gen) - e) < 0) {
-      __builtin_amdgcn_s_sleep(1);
-      if (ld_relaxed(tm.abort)) ok = 0;
-      else if (wall_clock64() - t0 > tm.spin_ticks) {
-        st_relaxed(tm.abort, 1u);
-        ok = 0;
+  if (!wait_flags(tm, tm.garr, ngroups, e)) return false;
+  for (int k = tid; k < K; k += BLOCK) {
+    double a = 0.0;
+    bool first = true;
+    for (int gb = 0; gb < ngroups; gb += 16) {
+      double v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = gb + q < ngroups ? gsum[(size_t)(gb + q) * PS + k] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        if (gb + q < ngroups) {
+          a = first ? v[q] : ((op == RED_SUM) ? a + v[q] : nanmax(a, v[q]));
+          first = false;
+        }
       }
     }
-    s_ok = ok;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    out[k] = a;
   }
-  __syncthreads();
-  if (!s_ok) return false;
-  for (int k = tid; k < K; k += BLOCK) out[k] = tm.result[k];
   __syncthreads();
   return true;
 }

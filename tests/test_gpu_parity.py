@@ -315,3 +315,28 @@ def test_fp32_basis_meets_gate(pk, name, build, p, t, tol):
     say("  gpu fp32", st, "rel", rel(u, ref))
     assert st["status"] == 0
     assert rel(u, ref) <= 10 * tol
+
+
+@pytest.mark.parametrize("case", ["ragged-3000", "convdiff-64", "lap2d-40"])
+@pytest.mark.parametrize("wg", [0, 4])
+def test_workspace_contents_do_not_matter(pk, case, wg):
+    """Nothing is read from the workspace before it is written: a workspace
+    filled with NaN bit patterns and one filled with zeros give bitwise
+    identical results."""
+    say("workspace fill", case, wg)
+    A = {"ragged-3000": lambda: ragged_matrix(3000, 7) * 0.05,
+         "convdiff-64": lambda: W.convdiff2d(64, 30.0, 30.0),
+         "lap2d-40": lambda: W.laplace2d(40)}[case]()
+    n = A.shape[0]
+    b = np.random.default_rng(12).standard_normal((n, 3))
+    Ad = pk.DeviceCSR(A)
+    bd = dev(b.T)
+    outs = []
+    for fill in (0, 255):
+        s = pk.Solver(Ad, 2, tol=1e-8, workgroups=wg)
+        s.ws.fill_(fill)
+        u = torch.empty(n, dtype=torch.float64, device="cuda")
+        st = s(0.05, bd, u)
+        assert st["status"] == 0
+        outs.append(u.cpu().numpy())
+    assert np.all(np.isfinite(outs[1])) and np.array_equal(outs[0], outs[1])
