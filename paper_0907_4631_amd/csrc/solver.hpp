@@ -127,7 +127,10 @@ struct Shared {
     SpmvSmem<double> sm64;
     SpmvSmem<float> sm32;
     double dense[DENSE_LDS];  // workgroup 0's small-matrix work
-    double wpart[NWAVES][KMAX];  // per-wave partial dot products (phase_dots)
+    struct {
+      double wpart[NWAVES][KMAX];  // per-wave partial dot products (phase_dots2)
+      double stage[2][BLOCK];      // u and w rows staged by phase_dots2
+    };
   };
   double blk[KMAX];
   double red[KMAX];
@@ -171,8 +174,11 @@ __device__ __forceinline__ SpmvSmem<float>& smem_for<float>(Shared& sh) { return
 // least one; with more jobs than wavefronts they go round robin), and a
 // wavefront streams its share of the workgroup's rows of that column in
 // 64-row chunks, so many independent loads are in flight; u and w are
-// re-read from L1.  Partial sums are reduced with DPP and then across a
-// job's wavefronts in a fixed order.
+// re-read from L1.  With more jobs than half the wavefronts and at most one
+// row per thread, u and w are staged in LDS instead and each wavefront
+// streams two of its columns per pass (the same per-job row order).  Partial
+// sums are reduced with DPP and then across a job's wavefronts in a fixed
+// order.
 template <typename T>
 __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, int K, const T* U,
                                             const T* Wv, bool with_u, int rb, int re,
@@ -184,29 +190,83 @@ __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, i
   const int seg = wv % wpj;
   // the rows of u and w were written by other threads of the workgroup
   __syncthreads();
-  for (int job = wv / wpj; job < jobs; job += NWAVES / wpj) {
-    double s0 = 0.0, s1 = 0.0;
-    if (job < K) {
-      const T* col = V + (long long)(i0 + job) * ldv;
-#pragma unroll 4
-      for (int r = rb + seg * WAVE + lane; r < re; r += WAVE * wpj) {
-        const double v = (double)col[r];
-        s0 += v * (double)Wv[r];
-        if (with_u) s1 += v * (double)U[r];
-      }
-    } else {
-#pragma unroll 4
-      for (int r = rb + seg * WAVE + lane; r < re; r += WAVE * wpj) {
-        const double ur = (double)U[r];
-        s0 += ur * ur;
-        s1 += ur * (double)Wv[r];
+  if (wpj == 1 && re - rb <= BLOCK) {
+    // more jobs than half the wavefronts and one row per thread: u and w
+    // are staged in LDS, and wavefront wv takes jobs wv, wv+16, ..., two
+    // per pass over the rows, so its global loads are basis columns only
+    // (per job the same row order as the path below)
+    constexpr int JC = 2;
+    {
+      const int r = rb + threadIdx.x;
+      if (r < re) {
+        sh.stage[0][threadIdx.x] = (double)U[r];
+        sh.stage[1][threadIdx.x] = (double)Wv[r];
       }
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    if (lane == 0) {
-      sh.wpart[seg][2 * job] = s0;
-      sh.wpart[seg][2 * job + 1] = s1;
+    __syncthreads();
+    const int nj = wv < jobs ? (jobs - wv + NWAVES - 1) / NWAVES : 0;
+    for (int t0 = 0; t0 < nj; t0 += JC) {
+      double s0[JC], s1[JC];
+#pragma unroll
+      for (int t = 0; t < JC; ++t) s0[t] = s1[t] = 0.0;
+      for (int r = rb + lane; r < re; r += WAVE) {
+        const double ur = sh.stage[0][r - rb], wr = sh.stage[1][r - rb];
+        double v[JC];
+#pragma unroll
+        for (int t = 0; t < JC; ++t) {
+          const int job = wv + (t0 + t) * NWAVES;
+          v[t] = (t0 + t < nj && job < K) ? (double)V[(long long)(i0 + job) * ldv + r] : ur;
+        }
+#pragma unroll
+        for (int t = 0; t < JC; ++t) {
+          if (t0 + t < nj) {
+            if (wv + (t0 + t) * NWAVES < K) {
+              s0[t] += v[t] * wr;
+              if (with_u) s1[t] += v[t] * ur;
+            } else {
+              s0[t] += ur * ur;
+              s1[t] += ur * wr;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < JC; ++t) {
+        if (t0 + t < nj) {
+          const double a0 = wave_sum(s0[t]), a1 = wave_sum(s1[t]);
+          const int job = wv + (t0 + t) * NWAVES;
+          if (lane == 0) {
+            sh.wpart[0][2 * job] = a0;
+            sh.wpart[0][2 * job + 1] = a1;
+          }
+        }
+      }
+    }
+  } else {
+    for (int job = wv / wpj; job < jobs; job += NWAVES / wpj) {
+      double s0 = 0.0, s1 = 0.0;
+      if (job < K) {
+        const T* col = V + (long long)(i0 + job) * ldv;
+#pragma unroll 4
+        for (int r = rb + seg * WAVE + lane; r < re; r += WAVE * wpj) {
+          const double v = (double)col[r];
+          s0 += v * (double)Wv[r];
+          if (with_u) s1 += v * (double)U[r];
+        }
+      } else {
+#pragma unroll 4
+        for (int r = rb + seg * WAVE + lane; r < re; r += WAVE * wpj) {
+          const double ur = (double)U[r];
+          s0 += ur * ur;
+          s1 += ur * (double)Wv[r];
+        }
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (lane == 0) {
+        sh.wpart[seg][2 * job] = s0;
+        sh.wpart[seg][2 * job + 1] = s1;
+      }
     }
   }
   __syncthreads();
@@ -249,7 +309,12 @@ __device__ __forceinline__ double second_pass(const Team& tm, const Work<T>& w, 
                                               Shared& sh) {
   const int K = j - zb;
   double ss = 0.0;
-  for (int k = 0; k < K; ++k) ss += sh.h1[k] * sh.h1[k];
+  {
+    // every wavefront forms the same sum (lanes over k, fixed DPP order)
+    double a = 0.0;
+    for (int k = threadIdx.x % WAVE; k < K; k += WAVE) a += sh.h1[k] * sh.h1[k];
+    ss = wave_sum(a);
+  }
   double b2 = a - ss;
   *applied = false;
   if (!(ss <= 0.25 * a) || !(b2 > 0.0)) {
@@ -358,7 +423,11 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
   const int ub = lanczos ? (j > 3 ? j - 3 : 0) : 0;
   const int KU = j - ub;
   double sdz = 0.0;
-  for (int k = 0; k < K; ++k) sdz += sh.h1[k] * sh.red[k];
+  {
+    double a = 0.0;
+    for (int k = threadIdx.x % WAVE; k < K; k += WAVE) a += sh.h1[k] * sh.red[k];
+    sdz = wave_sum(a);
+  }
   const double ib = 1.0 / beta;
   const double hjj = uf ? c : (c - sdz) * ib * ib - sj1;   // first pass, row j of column j
   {
@@ -392,10 +461,18 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
   T* vj = w.V + (long long)j * w.ldv;
   for (int r = rb + threadIdx.x; r < re; r += BLOCK) {
     double vs = 0.0, vq = 0.0;
-    for (int i = 0; i < KU; ++i) {
-      const double v = (double)w.V[(long long)(ub + i) * w.ldv + r];
-      vs += sh.wpart[0][i] * v;
-      vq += sh.qv[i] * v;
+    // two columns per iteration: their loads are issued together, the sums
+    // stay in column order
+    const T* vp = w.V + (long long)ub * w.ldv + r;
+    for (int i = 0; i < KU; i += 2) {
+      const double v0 = (double)vp[(long long)i * w.ldv];
+      const double v1 = i + 1 < KU ? (double)vp[(long long)(i + 1) * w.ldv] : 0.0;
+      vs += sh.wpart[0][i] * v0;
+      vq += sh.qv[i] * v0;
+      if (i + 1 < KU) {
+        vs += sh.wpart[0][i + 1] * v1;
+        vq += sh.qv[i + 1] * v1;
+      }
     }
     const double ur = (double)U[r];
     const T vjt = uf ? T(ur) : T((ur - vs) * ib);
