@@ -176,7 +176,8 @@ __device__ __forceinline__ SpmvSmem<float>& smem_for<float>(Shared& sh) { return
 // 64-row chunks, so many independent loads are in flight; u and w are
 // re-read from L1.  With more jobs than half the wavefronts and at most one
 // row per thread, u and w are staged in LDS instead and each wavefront
-// streams two of its columns per pass (the same per-job row order).  Partial
+// streams its columns with eight loads in flight per lane (the same per-job
+// row order).  Partial
 // sums are reduced with DPP and then across a job's wavefronts in a fixed
 // order.
 template <typename T>
@@ -192,10 +193,11 @@ __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, i
   __syncthreads();
   if (wpj == 1 && re - rb <= BLOCK) {
     // more jobs than half the wavefronts and one row per thread: u and w
-    // are staged in LDS, and wavefront wv takes jobs wv, wv+16, ..., two
-    // per pass over the rows, so its global loads are basis columns only
-    // (per job the same row order as the path below)
-    constexpr int JC = 2;
+    // are staged in LDS, and wavefront wv takes jobs wv, wv+16, ..., one per
+    // pass over the rows with eight rows of a lane loaded together, so its
+    // global loads are basis columns only (per job the same row order as the
+    // path below)
+    constexpr int JC = 1;  // jobs per pass over the rows
     {
       const int r = rb + threadIdx.x;
       if (r < re) {
@@ -205,27 +207,37 @@ __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, i
     }
     __syncthreads();
     const int nj = wv < jobs ? (jobs - wv + NWAVES - 1) / NWAVES : 0;
+    constexpr int RR = 8;  // rows per lane and iteration
     for (int t0 = 0; t0 < nj; t0 += JC) {
-      double s0[JC], s1[JC];
+      // a_t = sum v.w and b_t = sum v.u over the rows; the (u.u, u.w) job
+      // reads u as its column, so a = u.w and b = u.u there.  Slots past
+      // the wavefront's jobs read u too and are not stored.  No branches in
+      // the loop: JC x RR loads in flight per lane.
+      const T* src[JC];
 #pragma unroll
-      for (int t = 0; t < JC; ++t) s0[t] = s1[t] = 0.0;
-      for (int r = rb + lane; r < re; r += WAVE) {
-        const double ur = sh.stage[0][r - rb], wr = sh.stage[1][r - rb];
-        double v[JC];
+      for (int t = 0; t < JC; ++t) {
+        const int job = wv + (t0 + t) * NWAVES;
+        src[t] = (t0 + t < nj && job < K) ? V + (long long)(i0 + job) * ldv : U;
+      }
+      double a[JC], b[JC];
 #pragma unroll
-        for (int t = 0; t < JC; ++t) {
-          const int job = wv + (t0 + t) * NWAVES;
-          v[t] = (t0 + t < nj && job < K) ? (double)V[(long long)(i0 + job) * ldv + r] : ur;
+      for (int t = 0; t < JC; ++t) a[t] = b[t] = 0.0;
+      for (int r = rb + lane; r < re; r += RR * WAVE) {
+        double v[RR][JC];
+#pragma unroll
+        for (int q = 0; q < RR; ++q) {
+          const int rq = r + q * WAVE < re ? r + q * WAVE : r;
+#pragma unroll
+          for (int t = 0; t < JC; ++t) v[q][t] = (double)src[t][rq];
         }
 #pragma unroll
-        for (int t = 0; t < JC; ++t) {
-          if (t0 + t < nj) {
-            if (wv + (t0 + t) * NWAVES < K) {
-              s0[t] += v[t] * wr;
-              if (with_u) s1[t] += v[t] * ur;
-            } else {
-              s0[t] += ur * ur;
-              s1[t] += ur * wr;
+        for (int q = 0; q < RR; ++q) {
+          if (r + q * WAVE < re) {
+            const double ur = sh.stage[0][r + q * WAVE - rb], wr = sh.stage[1][r + q * WAVE - rb];
+#pragma unroll
+            for (int t = 0; t < JC; ++t) {
+              a[t] += v[q][t] * wr;
+              b[t] += v[q][t] * ur;
             }
           }
         }
@@ -233,11 +245,11 @@ __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, i
 #pragma unroll
       for (int t = 0; t < JC; ++t) {
         if (t0 + t < nj) {
-          const double a0 = wave_sum(s0[t]), a1 = wave_sum(s1[t]);
           const int job = wv + (t0 + t) * NWAVES;
+          const double x = wave_sum(a[t]), y = wave_sum(b[t]);
           if (lane == 0) {
-            sh.wpart[0][2 * job] = a0;
-            sh.wpart[0][2 * job + 1] = a1;
+            sh.wpart[0][2 * job] = job < K ? x : y;
+            sh.wpart[0][2 * job + 1] = job < K ? (with_u ? y : 0.0) : x;
           }
         }
       }
@@ -369,7 +381,7 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
         acc = spmv_tile<T, double>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), ld);
       } else {
         auto ld = [&](int c) -> double { return (double)U[c]; };
-        acc = spmv_tile<T, double>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), ld);
+        acc = spmv_tile<T, double, 8>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), ld);
       }
       const int r = r0 + threadIdx.x;
       if (r < r1) {
