@@ -63,6 +63,7 @@ struct BatchArgs {
   Stats* stats;       // [count]
   unsigned long long* clk;  // [2 count] start and end of each instance (wall clock)
   WorkLayout wl;      // layout of every team's work buffer
+  double* hpool;      // [grid] copies of H, one per workgroup
   double tol, tau_fixed;
   long long max_attempts;
   int ncls, symm, m_init, m_max, adapt_m, corrector, validate, pad;
@@ -126,7 +127,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
     w.ldv = a.wl.ld;
     w.y0 = reinterpret_cast<T*>(base + a.wl.y0);
     w.y1 = reinterpret_cast<T*>(base + a.wl.y1);
-    w.H = reinterpret_cast<double*>(base + a.wl.H);
+    w.H = a.hpool + (size_t)tr.first * H_WORDS;  // the team leader's copy
+    w.Hm = a.hpool + (size_t)blockIdx.x * H_WORDS;
     w.ex = reinterpret_cast<double*>(base + a.wl.ex);
     w.st = reinterpret_cast<State*>(base + a.wl.st);
   }
@@ -347,6 +349,7 @@ struct phipm_plan {
   TeamRec* d_teams = nullptr;
   int* d_team_of = nullptr;
   char* d_ws = nullptr;
+  double* d_hpool = nullptr;
   unsigned* d_flags = nullptr;
   size_t nflags = 0;
   size_t npart = 0;
@@ -412,6 +415,7 @@ int set_layout(phipm_plan* pl, const TeamLayout& L, hipStream_t stream) {
   a.stats = pl->d_stats;
   a.clk = pl->d_clk;
   a.wl = pl->wl;
+  a.hpool = pl->d_hpool;
   a.tol = pl->opts.tol;
   a.tau_fixed = pl->opts.tau_fixed;
   a.max_attempts = pl->opts.max_attempts;
@@ -674,10 +678,11 @@ int phipm_plan_create(int count, const phipm_csr* A, const int32_t* p, const dou
   }
   // one allocation for everything the plan keeps on the device
   const int G = pl->grid;
-  pl->wl = work_layout(nmax, nnzmax, pmax, std::min(o->m_max, nmax), pl->fp32);
+  pl->wl = work_layout(nmax, nnzmax, pmax, std::min(o->m_max, nmax), pl->fp32, 0);
   pl->team_ws = pl->wl.total;
   pl->nflags = (size_t)FLAG_STRIDE * 3 * (size_t)G;
-  pl->npart = (size_t)KMAX * 4 * (size_t)G;  // >= sum over teams of team_partials(size) + KMAX
+  // >= sum over teams of team_partials(size) + KMAX (teams of one: 1 + TEAM_GBUF + 1 rows)
+  pl->npart = (size_t)KMAX * (2 + TEAM_GBUF) * (size_t)G;
   const size_t npart = pl->npart;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o2 = off; off = align256(off + bytes); return o2; };
@@ -693,6 +698,7 @@ int phipm_plan_create(int count, const phipm_csr* A, const int32_t* p, const dou
   const size_t o_stats = take(sizeof(Stats) * count);
   const size_t o_clk = take(sizeof(unsigned long long) * 2 * count);
   const size_t o_norms = take(sizeof(double) * count);
+  const size_t o_hpool = take(sizeof(double) * H_WORDS * (size_t)G);
   const size_t o_ws = take(pl->team_ws * (size_t)G);
   pl->mem_bytes = off;
   if (hipMalloc(&pl->mem, off) != hipSuccess) {
@@ -715,6 +721,7 @@ int phipm_plan_create(int count, const phipm_csr* A, const int32_t* p, const dou
   pl->d_clk = reinterpret_cast<unsigned long long*>(base + o_clk);
   pl->d_norms = reinterpret_cast<double*>(base + o_norms);
   pl->d_ws = base + o_ws;
+  pl->d_hpool = reinterpret_cast<double*>(base + o_hpool);
   int rc = PHIPM_OK;
   pl->anorm.assign(count, 0.0);
   if (hipMemcpyAsync(pl->d_inst, pl->inst.data(), sizeof(Inst) * count, hipMemcpyHostToDevice,

@@ -33,7 +33,9 @@ struct WorkLayout {
 // The basis and its two work vectors are sized for float64 also with the
 // FP32 basis, which falls back to the FP64 basis in the same buffer when its
 // rounding estimate runs over budget.
-inline WorkLayout work_layout(int n, int nnz, int p, int m_cap, bool fp32) {
+// hcopies: copies of H (one per workgroup of the launch; 0 when the caller
+// places them elsewhere).
+inline WorkLayout work_layout(int n, int nnz, int p, int m_cap, bool fp32, int hcopies) {
   WorkLayout L{};
   const size_t tb = 8;
   L.ld = pad64(n);
@@ -44,7 +46,7 @@ inline WorkLayout work_layout(int n, int nnz, int p, int m_cap, bool fp32) {
   L.y0 = take(tb * (size_t)L.ld);
   L.y1 = take(tb * (size_t)L.ld);
   L.val32 = take(fp32 ? sizeof(float) * (size_t)std::max(nnz, 1) : 0);
-  L.H = take(sizeof(double) * (M_CAP + 1) * M_CAP);
+  L.H = take(sizeof(double) * H_WORDS * (size_t)hcopies);
   L.ex = take(sizeof(double) * 8 * (size_t)NMAX_EXPM * NMAX_EXPM);
   L.st = take(sizeof(State));
   L.stats = take(sizeof(Stats));
@@ -57,7 +59,8 @@ inline Work<T> work_at(char* base, const WorkLayout& L) {
   return Work<T>{reinterpret_cast<double*>(base + L.W), L.ld, reinterpret_cast<T*>(base + L.V),
                  L.ld, reinterpret_cast<T*>(base + L.y0), reinterpret_cast<T*>(base + L.y1),
                  reinterpret_cast<double*>(base + L.H), reinterpret_cast<double*>(base + L.ex),
-                 reinterpret_cast<State*>(base + L.st), reinterpret_cast<Stats*>(base + L.stats)};
+                 reinterpret_cast<State*>(base + L.st), reinterpret_cast<Stats*>(base + L.stats),
+                 reinterpret_cast<double*>(base + L.H)};
 }
 
 inline bool opts_ok(const phipm_opts* o) {

@@ -29,7 +29,9 @@ __global__ __launch_bounds__(BLOCK) void k_solve(Problem P, Work<T> w, TeamCtl* 
   __shared__ Shared sh;
   const Team tm = make_team((int)blockIdx.x, (int)gridDim.x, &ctl->gen, &ctl->abort, partials,
                             result, spin);
-  solve_mixed<T>(tm, P, w, sh);
+  Work<T> wk = w;
+  wk.Hm = w.H + (size_t)blockIdx.x * H_WORDS;
+  solve_mixed<T>(tm, P, wk, sh);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_spmv(int n, const int* rp, const int* ci,
@@ -55,15 +57,25 @@ __global__ __launch_bounds__(BLOCK) void k_expm(int N, const double* H, double* 
 }
 
 // m Krylov steps from v with the solver's step routine (float64).
-__global__ __launch_bounds__(BLOCK) void k_krylov(Problem P, Work<double> w, const double* v,
+__global__ __launch_bounds__(BLOCK) void k_krylov(Problem P, Work<double> w0, const double* v,
                                                   int m, int lanczos, double* Hout,
                                                   int* m_done, TeamCtl* ctl, double* partials,
                                                   double* result, unsigned long long spin) {
   __shared__ Shared sh;
   const Team tm = make_team((int)blockIdx.x, (int)gridDim.x, &ctl->gen, &ctl->abort, partials,
                             result, spin);
+  Work<double> w = w0;
+  w.Hm = w0.H + (size_t)blockIdx.x * H_WORDS;
   int rb, re;
   own_rows(tm, P.n, rb, re);
+  // the column range of the own rows: every slot (this entry point skips
+  // the solver's setup scan)
+  if (threadIdx.x == 0) {
+    sh.dep_lo = 0;
+    sh.dep_hi = tm.size - 1;
+  }
+  for (size_t e = threadIdx.x; e < H_WORDS; e += BLOCK) w.Hm[e] = 0.0;
+  __syncthreads();
   double a = 0.0;
   for (int r = rb + threadIdx.x; r < re; r += BLOCK) a += v[r] * v[r];
   double a1[1] = {a};
@@ -135,9 +147,9 @@ struct Layout {
   size_t ctl, part, res, total;
 };
 
-Layout layout(int n, int nnz, int p, int m_cap, bool fp32, int gmax) {
+Layout layout(int n, int nnz, int p, int m_cap, bool fp32, int gmax, int groups) {
   Layout L{};
-  L.w = work_layout(n, nnz, p, m_cap, fp32);
+  L.w = work_layout(n, nnz, p, m_cap, fp32, groups);
   size_t off = L.w.total;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   L.ctl = take(sizeof(TeamCtl));
@@ -196,7 +208,7 @@ int phipm_workspace_bytes(const phipm_csr* A, int p, const phipm_opts* o, size_t
   const bool fp32 = o->precision == PHIPM_FP32_BASIS;
   const int gmax = fp32 ? d->coresident32 : d->coresident64;
   const int m_cap = std::min(o->m_max, A->n);
-  *bytes = layout(A->n, A->nnz, p, m_cap, fp32, gmax).total;
+  *bytes = layout(A->n, A->nnz, p, m_cap, fp32, gmax, choose_workgroups(o, A->n, gmax)).total;
   return PHIPM_OK;
 }
 
@@ -212,7 +224,8 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   const bool fp32 = o->precision == PHIPM_FP32_BASIS;
   const int gmax = fp32 ? d->coresident32 : d->coresident64;
   const int m_cap = std::min(o->m_max, A->n);
-  const Layout L = layout(A->n, A->nnz, p, m_cap, fp32, gmax);
+  const int G = choose_workgroups(o, A->n, gmax);
+  const Layout L = layout(A->n, A->nnz, p, m_cap, fp32, gmax, G);
   if (ws_bytes < L.total) return fail(PHIPM_ENOMEM);
   // u must not overlap b or the workspace
   const size_t ub = sizeof(double) * (size_t)A->n;
@@ -251,7 +264,6 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   double* res = reinterpret_cast<double*>(ws + L.res);
   Stats* dstats = reinterpret_cast<Stats*>(ws + L.w.stats);
   unsigned long long spin = d->spin_ticks;
-  const int G = choose_workgroups(o, A->n, gmax);
 
   hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1);
   if (hipGetLastError() != hipSuccess) return fail(PHIPM_EHIP);
@@ -326,7 +338,10 @@ int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return PHIPM_EINVAL;
   const DeviceInfo* d = device_info();
   if (!d) return PHIPM_EHIP;
-  const Layout L = layout(A->n, A->nnz, 0, m, false, d->coresident64);
+  phipm_opts o;
+  phipm_default_opts(&o);
+  const int G = choose_workgroups(&o, A->n, d->coresident64);
+  const Layout L = layout(A->n, A->nnz, 0, m, false, d->coresident64, G);
   if (ws_bytes < L.total) return PHIPM_ENOMEM;
   char* ws = static_cast<char*>(workspace);
   Problem P{};
@@ -337,15 +352,13 @@ int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double
   P.val = A->val;
   Work<double> w{nullptr, 0, V, A->n, reinterpret_cast<double*>(ws + L.w.y0),
                  reinterpret_cast<double*>(ws + L.w.y1), reinterpret_cast<double*>(ws + L.w.H),
-                 nullptr, reinterpret_cast<State*>(ws + L.w.st), nullptr};
+                 nullptr, reinterpret_cast<State*>(ws + L.w.st), nullptr,
+                 reinterpret_cast<double*>(ws + L.w.H)};
   TeamCtl* ctl = reinterpret_cast<TeamCtl*>(ws + L.ctl);
   double* part = reinterpret_cast<double*>(ws + L.part);
   double* res = reinterpret_cast<double*>(ws + L.res);
   int* dm = reinterpret_cast<int*>(ws + L.w.stats);
   unsigned long long spin = d->spin_ticks;
-  phipm_opts o;
-  phipm_default_opts(&o);
-  const int G = choose_workgroups(&o, A->n, d->coresident64);
   hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1);
   void* args[] = {&P, &w, &v, &m, &lanczos, &H, &dm, &ctl, &part, &res, &spin};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_krylov), dim3(G), dim3(BLOCK),

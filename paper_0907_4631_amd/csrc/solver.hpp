@@ -116,11 +116,15 @@ struct Work {
   long long ldv;
   T* y0;
   T* y1;
-  double* H;
+  double* H;    // Hessenberg matrix, row stride M_CAP: workgroup 0's copy
   double* ex;
   State* st;
   Stats* stats;
+  double* Hm;   // this workgroup's copy of H (== H in workgroup 0)
 };
+
+// Doubles of one copy of H.
+constexpr size_t H_WORDS = (size_t)(M_CAP + 1) * M_CAP;
 
 struct Shared {
   union {
@@ -138,6 +142,7 @@ struct Shared {
   double qv[KMAX];
   double coef[P_MAX + 1];
   double yb[M_CAP + 2];
+  int dep_lo, dep_hi;  // row-block slots whose rows this workgroup's products read
 };
 
 // Algorithmic HBM bytes of one CSR product y = A x with value/vector width s.
@@ -149,11 +154,15 @@ __device__ __forceinline__ double spmv_bytes(const Problem& P, double s) {
 // blocks are dealt so that the workgroups of one XCD (hardware block ids
 // congruent mod 8) hold neighbouring rows: the stencil gathers then stay in
 // that XCD's L2.
+// Rows per slot: an equal share padded to 64.
+__device__ __forceinline__ long long row_chunk(int n, int size) {
+  const long long chunk = ((long long)n + size - 1) / size;
+  return (chunk + 63) / 64 * 64;
+}
+
 __device__ __forceinline__ void own_rows(const Team& tm, int n, int& rb, int& re) {
-  int slot = tm.rank;
-  if (tm.size % 8 == 0) slot = (tm.rank % 8) * (tm.size / 8) + tm.rank / 8;
-  long long chunk = ((long long)n + tm.size - 1) / tm.size;
-  chunk = (chunk + 63) / 64 * 64;
+  const int slot = team_slot(tm.rank, tm.size);
+  const long long chunk = row_chunk(n, tm.size);
   long long b = (long long)slot * chunk;
   rb = (int)(b < n ? b : n);
   long long e = b + chunk;
@@ -411,13 +420,13 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
   }
   const double sj1 = (!uf && j > 0) ? sh.h1[K - 1] : 0.0;   // s_{j-1}
   if (!uf && beta <= bd_tol) {
-    // invariant subspace: finalise column j-1; there is no v_j.  No
-    // workgroup reads H in this iteration, so workgroup 0 writes it now.
-    if (tm.rank == 0) {
-      for (int i = threadIdx.x; i < j; i += BLOCK)
-        if (i >= zb) w.H[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
-      if (threadIdx.x == 0) {
-        w.H[(long long)j * M_CAP + (j - 1)] = beta;
+    // invariant subspace: finalise column j-1 (every workgroup in its own
+    // copy of H); there is no v_j
+    for (int i = threadIdx.x; i < j; i += BLOCK)
+      if (i >= zb) w.Hm[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
+    if (threadIdx.x == 0) {
+      w.Hm[(long long)j * M_CAP + (j - 1)] = beta;
+      if (tm.rank == 0) {
         w.st->matvecs += 1;
         w.st->bytes += spmv_bytes(P, sizeof(T)) + (K + 2.0) * sizeof(T) * (double)P.n;
       }
@@ -452,7 +461,7 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
       if (!uf) {
         for (int k = lane; k < K; k += WAVE) {
           const int col = zb + k;
-          if (row <= col + 1) g += w.H[(long long)row * M_CAP + col] * sh.h1[k];
+          if (row <= col + 1) g += w.Hm[(long long)row * M_CAP + col] * sh.h1[k];
         }
         g = wave_sum(g);
         if (row >= zb) g += sh.h1[row - zb] * sj1;
@@ -468,6 +477,24 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
     }
   }
   __syncthreads();
+  // this workgroup's copy of H (g above has read it): column j-1 final,
+  // column j first pass in rows [ub, j]; its other rows stay zero from the
+  // solve's setup (a column never has entries outside its window and the
+  // subdiagonal)
+  for (int i = threadIdx.x; i <= j; i += BLOCK) {
+    if (!uf && j > 0 && i < j && i >= zb) w.Hm[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
+    if (i >= ub) w.Hm[(long long)i * M_CAP + j] = i < j ? sh.blk[i - ub] : hjj;
+  }
+  if (threadIdx.x == 0) {
+    if (!uf && j > 0) w.Hm[(long long)j * M_CAP + (j - 1)] = beta;
+    if (tm.rank == 0) {
+      w.st->matvecs += 1;
+      // product (+ the v_0 store), the fused dots (K columns, u, w), the
+      // row-local pass (KU columns, u, w read; v_j, u written)
+      w.st->bytes += spmv_bytes(P, sizeof(T)) + (seed ? 2.0 : 0.0) * sizeof(T) * (double)P.n +
+                     (K + 2.0 + KU + 2.0 + (uf ? 1.0 : 2.0)) * sizeof(T) * (double)P.n;
+    }
+  }
   // P3: row-local pass, then publish u_{j+1}
   const double tj = sj1 + hjj;
   T* vj = w.V + (long long)j * w.ldv;
@@ -491,27 +518,9 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
     if (!uf) vj[r] = vjt;
     U[r] = T((double)Wv[r] * ib - vq - tj * (double)vjt);
   }
-  if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return false;
-  if (tm.rank == 0) {
-    // every workgroup has read H for g: column j-1 final, column j first
-    // pass (rows outside the window zeroed)
-    for (int i = threadIdx.x; i <= M_CAP; i += BLOCK) {
-      if (!uf && j > 0 && i < j && i >= zb) w.H[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
-      double hv = 0.0;
-      if (i >= ub && i < j) hv = sh.blk[i - ub];
-      else if (i == j) hv = hjj;
-      w.H[(long long)i * M_CAP + j] = hv;
-    }
-    if (threadIdx.x == 0) {
-      if (!uf && j > 0) w.H[(long long)j * M_CAP + (j - 1)] = beta;
-      w.st->matvecs += 1;
-      // product (+ the v_0 store), the fused dots (K columns, u, w), the
-      // row-local pass (KU columns, u, w read; v_j, u written)
-      w.st->bytes += spmv_bytes(P, sizeof(T)) + (seed ? 2.0 : 0.0) * sizeof(T) * (double)P.n +
-                     (K + 2.0 + KU + 2.0 + (uf ? 1.0 : 2.0)) * sizeof(T) * (double)P.n;
-    }
-    __syncthreads();
-  }
+  // the next product reads u_{j+1} only in the rows of the slots this
+  // workgroup depends on
+  if (!team_neighbor_sync(tm, sh.dep_lo, sh.dep_hi)) return false;
   kc.have = j + 1;
   kc.u_final = 0;
   kc.final_col = 0;
@@ -539,13 +548,11 @@ __device__ __forceinline__ bool krylov_finalize(const Team& tm, const Problem& P
   bool applied = false;
   const double beta = second_pass<T>(tm, w, zb, j, a, U, rb, re, &applied, sh);
   if (beta < 0.0) return false;
-  if (tm.rank == 0) {
-    for (int i = threadIdx.x; i < j; i += BLOCK)
-      if (i >= zb) w.H[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
-    if (threadIdx.x == 0) {
-      w.H[(long long)j * M_CAP + (j - 1)] = beta;
-      w.st->bytes += (K + 1.0) * sizeof(T) * (double)P.n;
-    }
+  for (int i = threadIdx.x; i < j; i += BLOCK)
+    if (i >= zb) w.Hm[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
+  if (threadIdx.x == 0) {
+    w.Hm[(long long)j * M_CAP + (j - 1)] = beta;
+    if (tm.rank == 0) w.st->bytes += (K + 1.0) * sizeof(T) * (double)P.n;
   }
   kc.final_col = 1;
   if (beta <= bd_tol) {
@@ -874,6 +881,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
   {
     // structure / finiteness / symmetry flags and the row sums of |A|
     double f[4] = {0.0, 0.0, 0.0, 0.0};  // bad, nonfinite, asym, max row sum
+    int cmin = n, cmax = -1;             // columns the own rows reference
     const bool check_sym = P.symm < 0;
     for (int r = rb + tid; r < re; r += BLOCK) {
       const int k0 = P.rp[r], k1 = P.rp[r + 1];
@@ -895,6 +903,8 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
           row_ok = false;
         } else {
           prev = c;
+          cmin = c < cmin ? c : cmin;
+          cmax = c > cmax ? c : cmax;
           if (!isfinite(a)) f[1] = 1.0;
           s += fabs(a);
           if (fp32) P.val32[k] = (float)a;
@@ -920,6 +930,27 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       f[3] = nanmax(f[3], s);
     }
     block_reduce<4>(f, RED_MAX, sh.blk);
+    // this workgroup's copy of H starts at zero: the Krylov steps write only
+    // each column's window and subdiagonal
+    for (size_t e = tid; e < H_WORDS; e += BLOCK) w.Hm[e] = 0.0;
+    {
+      // slots owning the referenced columns: the rows a product here reads
+      double cr[2] = {-(double)cmin, (double)cmax};
+      block_reduce<2>(cr, RED_MAX, sh.h1);
+      if (tid == 0) {
+        const long long chunk = row_chunk(n, tm.size);
+        const long long lo = (long long)(-sh.h1[0]), hi = (long long)sh.h1[1];
+        if (hi < lo || hi < 0) {
+          sh.dep_lo = 1;
+          sh.dep_hi = 0;
+        } else {
+          const long long slo = (lo < 0 ? 0 : lo) / chunk, shi = (hi >= n ? n - 1 : hi) / chunk;
+          sh.dep_lo = (int)slo;
+          sh.dep_hi = (int)(shi < tm.size - 1 ? shi : tm.size - 1);
+        }
+      }
+      __syncthreads();
+    }
     // max |b_k| for every k (one block reduction per column)
     for (int k = 0; k <= p; ++k) {
       double bm[1] = {0.0};
@@ -1222,7 +1253,7 @@ __device__ __forceinline__ int solve_mixed(const Team& tm, const Problem& P, con
       }
       Work<double> wd{w.W, w.ldw, reinterpret_cast<double*>(w.V), w.ldv,
                       reinterpret_cast<double*>(w.y0), reinterpret_cast<double*>(w.y1), w.H,
-                      w.ex, w.st, w.stats};
+                      w.ex, w.st, w.stats, w.Hm};
       r = solve<double>(tm, P, wd, sh);
       if (r == SOLVE_DONE && tm.rank == 0 && threadIdx.x == 0) {
         Stats* o = w.stats;

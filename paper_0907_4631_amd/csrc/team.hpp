@@ -20,6 +20,7 @@ constexpr int TEAM_GROUP = 16;            // workgroups per arrival group
 constexpr int TEAM_MAX = 1024;            // largest team
 constexpr int TEAM_NGROUPS = TEAM_MAX / TEAM_GROUP;
 constexpr int FLAG_STRIDE = 32;           // one flag per 128-byte line
+constexpr int TEAM_GBUF = 4;              // group-sum buffers, used round robin by epoch
 
 // Team control block in device memory (zeroed before every launch).  Every
 // workgroup posts the epoch it reached in its own flag; the first workgroup
@@ -42,7 +43,7 @@ struct Team {
   unsigned* abort;     // abort flag shared by every team of the launch
   unsigned* garr;      // group leaders' epochs, FLAG_STRIDE apart
   unsigned* arr;       // members' epochs, FLAG_STRIDE apart
-  double* partials;    // [size][KMAX] per-workgroup values, then 2 x [groups][KMAX] group sums
+  double* partials;    // [size][KMAX] per-workgroup values, then TEAM_GBUF x [groups][KMAX] group sums
   double* result;      // [KMAX]
   uint64_t spin_ticks; // wall-clock budget of one wait
 };
@@ -72,7 +73,7 @@ __device__ __forceinline__ Team make_team(int rank, int size, unsigned* flags, u
 
 // Partials a team needs (doubles).
 __host__ __device__ inline size_t team_partials(int size) {
-  return (size_t)KMAX * (size + 2 * ((size + TEAM_GROUP - 1) / TEAM_GROUP));
+  return (size_t)KMAX * (size + TEAM_GBUF * ((size + TEAM_GROUP - 1) / TEAM_GROUP));
 }
 
 enum RedOp { RED_SUM = 0, RED_MAX = 1 };
@@ -273,11 +274,13 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
     __syncthreads();
     return true;
   }
-  // group sums alternate between two buffers by epoch parity: a leader may
-  // write the next sync's sums while a slower workgroup of another group
-  // still reads this one's, but not two syncs ahead (it would need that
-  // workgroup's arrival)
-  double* gsum = tm.partials + ((size_t)tm.size + (size_t)(e & 1u) * ngroups) * PS;
+  // group sums rotate over TEAM_GBUF buffers by epoch: a leader may write a
+  // later sync's sums while a slower workgroup of another group still reads
+  // this one's, as long as only neighbour synchronisations (which do not
+  // wait for that workgroup) lie between the two; the solver never has more
+  // than one in a row
+  double* gsum =
+      tm.partials + ((size_t)tm.size + (size_t)(e % (unsigned)TEAM_GBUF) * ngroups) * PS;
   const int grp = tm.rank / TEAM_GROUP;
   const int g0 = grp * TEAM_GROUP;
   const int gsz = tm.size - g0 < TEAM_GROUP ? tm.size - g0 : TEAM_GROUP;
@@ -320,6 +323,69 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
   }
   __syncthreads();
   return true;
+}
+
+// Row-block slot of a team rank and its inverse.  With a team size that is
+// a multiple of 8, ranks with equal rank mod 8 (the workgroups of one XCD
+// when the team starts at a multiple of 8) get neighbouring slots.
+__host__ __device__ inline int team_slot(int rank, int size) {
+  return size % 8 == 0 ? (rank % 8) * (size / 8) + rank / 8 : rank;
+}
+__host__ __device__ inline int team_rank_of_slot(int slot, int size) {
+  return size % 8 == 0 ? (slot % (size / 8)) * 8 + slot / (size / 8) : slot;
+}
+
+// Neighbour synchronisation: this workgroup posts its next epoch, then waits
+// until the workgroups owning row-block slots [slo, shi] have posted it too
+// (an empty range waits for nobody).  Publishes this workgroup's earlier
+// global writes to those that wait for it; it orders nothing else, so it
+// replaces a barrier only where the data that follows depends on those
+// slots alone.  Returns false if the team was aborted.
+__device__ __forceinline__ bool team_neighbor_sync(const Team& tm, int slo, int shi) {
+  __shared__ unsigned s_epoch;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  if (tm.size == 1) {
+    __syncthreads();
+    return true;
+  }
+  unsigned* my = tm.arr + (size_t)tm.rank * FLAG_STRIDE;
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned e = ld_relaxed(my) + 1u;
+    s_epoch = e;
+    s_bad = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    st_relaxed(my, e);
+  }
+  __syncthreads();
+  const unsigned e = s_epoch;
+  const int cnt = shi - slo + 1;
+  const int lane = tid % WAVE, wv = tid / WAVE;
+  if (cnt > 0 && wv * WAVE < cnt) {
+    const int i = wv * WAVE + lane;
+    const unsigned* f =
+        i < cnt ? tm.arr + (size_t)team_rank_of_slot(slo + i, tm.size) * FLAG_STRIDE : nullptr;
+    const uint64_t t0 = wall_clock64();
+    int all = 0, bad = 0;
+    while (!all && !bad) {
+      const unsigned v = f ? ld_relaxed(const_cast<unsigned*>(f)) : e;
+      all = __all((int)(v - e) >= 0);
+      if (!all) {
+        __builtin_amdgcn_s_sleep(1);
+        if (ld_relaxed(tm.abort)) bad = 1;
+        else if (wall_clock64() - t0 > tm.spin_ticks) {
+          st_relaxed(tm.abort, 1u);
+          bad = 1;
+        }
+      }
+    }
+    if (bad && lane == 0) s_bad = 1;
+  }
+  __syncthreads();
+  if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return s_bad == 0;
 }
 
 }  // namespace pkr
