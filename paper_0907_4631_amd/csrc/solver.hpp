@@ -142,8 +142,17 @@ struct Shared {
   double qv[KMAX];
   double coef[P_MAX + 1];
   double yb[M_CAP + 2];
+  double hcol[M_CAP + 1];  // first-pass entries of the newest column of H
   int dep_lo, dep_hi;  // row-block slots whose rows this workgroup's products read
 };
+
+// Statistics updates from the Krylov steps (workgroup 0, one thread): no-return
+// atomics, so the thread does not wait for the old values.
+__device__ __forceinline__ void add_matvec(State* st, double bytes) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(&st->matvecs), 1ull);
+  atomicAdd(&st->bytes, bytes);
+}
+__device__ __forceinline__ void add_bytes(State* st, double bytes) { atomicAdd(&st->bytes, bytes); }
 
 // Algorithmic HBM bytes of one CSR product y = A x with value/vector width s.
 __device__ __forceinline__ double spmv_bytes(const Problem& P, double s) {
@@ -423,12 +432,11 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
     // invariant subspace: finalise column j-1 (every workgroup in its own
     // copy of H); there is no v_j
     for (int i = threadIdx.x; i < j; i += BLOCK)
-      if (i >= zb) w.Hm[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
+      if (i >= zb) w.Hm[(long long)i * M_CAP + (j - 1)] = sh.hcol[i] + sh.h1[i - zb];
     if (threadIdx.x == 0) {
       w.Hm[(long long)j * M_CAP + (j - 1)] = beta;
       if (tm.rank == 0) {
-        w.st->matvecs += 1;
-        w.st->bytes += spmv_bytes(P, sizeof(T)) + (K + 2.0) * sizeof(T) * (double)P.n;
+        add_matvec(w.st, spmv_bytes(P, sizeof(T)) + (K + 2.0) * sizeof(T) * (double)P.n);
       }
     }
     __syncthreads();
@@ -481,18 +489,21 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
   // column j first pass in rows [ub, j]; its other rows stay zero from the
   // solve's setup (a column never has entries outside its window and the
   // subdiagonal)
+  // (sh.hcol holds column j-1's first pass and takes column j's)
   for (int i = threadIdx.x; i <= j; i += BLOCK) {
-    if (!uf && j > 0 && i < j && i >= zb) w.Hm[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
-    if (i >= ub) w.Hm[(long long)i * M_CAP + j] = i < j ? sh.blk[i - ub] : hjj;
+    if (!uf && j > 0 && i < j && i >= zb)
+      w.Hm[(long long)i * M_CAP + (j - 1)] = sh.hcol[i] + sh.h1[i - zb];
+    const double hv = i < ub ? 0.0 : (i < j ? sh.blk[i - ub] : hjj);
+    if (i >= ub) w.Hm[(long long)i * M_CAP + j] = hv;
+    sh.hcol[i] = hv;
   }
   if (threadIdx.x == 0) {
     if (!uf && j > 0) w.Hm[(long long)j * M_CAP + (j - 1)] = beta;
     if (tm.rank == 0) {
-      w.st->matvecs += 1;
       // product (+ the v_0 store), the fused dots (K columns, u, w), the
       // row-local pass (KU columns, u, w read; v_j, u written)
-      w.st->bytes += spmv_bytes(P, sizeof(T)) + (seed ? 2.0 : 0.0) * sizeof(T) * (double)P.n +
-                     (K + 2.0 + KU + 2.0 + (uf ? 1.0 : 2.0)) * sizeof(T) * (double)P.n;
+      add_matvec(w.st, spmv_bytes(P, sizeof(T)) + (seed ? 2.0 : 0.0) * sizeof(T) * (double)P.n +
+                           (K + 2.0 + KU + 2.0 + (uf ? 1.0 : 2.0)) * sizeof(T) * (double)P.n);
     }
   }
   // P3: row-local pass, then publish u_{j+1}
@@ -549,10 +560,10 @@ __device__ __forceinline__ bool krylov_finalize(const Team& tm, const Problem& P
   const double beta = second_pass<T>(tm, w, zb, j, a, U, rb, re, &applied, sh);
   if (beta < 0.0) return false;
   for (int i = threadIdx.x; i < j; i += BLOCK)
-    if (i >= zb) w.Hm[(long long)i * M_CAP + (j - 1)] += sh.h1[i - zb];
+    if (i >= zb) w.Hm[(long long)i * M_CAP + (j - 1)] = sh.hcol[i] + sh.h1[i - zb];
   if (threadIdx.x == 0) {
     w.Hm[(long long)j * M_CAP + (j - 1)] = beta;
-    if (tm.rank == 0) w.st->bytes += (K + 1.0) * sizeof(T) * (double)P.n;
+    if (tm.rank == 0) add_bytes(w.st, (K + 1.0) * sizeof(T) * (double)P.n);
   }
   kc.final_col = 1;
   if (beta <= bd_tol) {
@@ -570,7 +581,7 @@ __device__ __forceinline__ bool krylov_finalize(const Team& tm, const Problem& P
     vh[r] = v;
     U[r] = v;
   }
-  if (tm.rank == 0 && threadIdx.x == 0) w.st->bytes += (K + 3.0) * sizeof(T) * (double)P.n;
+  if (tm.rank == 0 && threadIdx.x == 0) add_bytes(w.st, (K + 3.0) * sizeof(T) * (double)P.n);
   __syncthreads();
   kc.u_final = 1;
   return true;
