@@ -132,13 +132,26 @@ __device__ __forceinline__ unsigned pivot_key(double v, int row) {
   return (f & 0xffffff00u) | (255u - (unsigned)row);
 }
 
+// Wave-wide unsigned max with DPP (same pattern as wave_sum); the result is
+// returned to every lane.
+__device__ __forceinline__ unsigned wave_umax(unsigned v) {
+  auto mx = [](unsigned a, int b) { return a > (unsigned)b ? a : (unsigned)b; };
+  v = mx(v, __builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false));
+  v = mx(v, __builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false));
+  v = mx(v, __builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));
+  v = mx(v, __builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));
+  v = mx(v, __builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+  v = mx(v, __builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Solve P X = Q in place (X overwrites Q) by Gauss-Jordan elimination with
 // partial pivoting.  For N <= 128 the system is stored by columns, lanes own
 // rows (i and i+64) and waves own columns, so every column is updated by a
 // single wave: the pivot row and row k are read in place (each lane's update
 // depends on them, so its loads complete before its stores) and the row
 // exchange is folded into the update.  Wave 0, which owns column k+1, posts
-// the candidates for the next pivot with LDS atomic max on pivot keys.  One
+// the next pivot: the wave-wide maximum of its candidates' pivot keys.  One
 // barrier per column.  [P | Q] lives in LDS when it fits; otherwise P does
 // and Q is kept by columns in the device scratch Wk (N x N doubles, L2
 // resident).
@@ -155,7 +168,6 @@ __device__ __forceinline__ void gj_eliminate(int N, double* M, int ld, double* G
   const bool r0 = i0 < N, r1 = i1 < N;
   for (int k = 0; k < N; ++k) {
     const int piv = 255 - (int)(s_key[k & 1] & 0xffu);
-    if (tid == 0) s_key[(k + 1) & 1] = 0u;
     const double* colk = M + k * ld;
     const double inv = 1.0 / colk[piv];
     const double kk = colk[k];
@@ -168,9 +180,11 @@ __device__ __forceinline__ void gj_eliminate(int N, double* M, int ld, double* G
       const double a1 = r1 ? col[i1] : 0.0;
       const double v0 = i0 == k ? pr : (i0 == piv ? kj - kk * pr : a0 - f0 * pr);
       const double v1 = i1 == k ? pr : (i1 == piv ? kj - kk * pr : a1 - f1 * pr);
-      if (cand) {  // candidates for the next pivot: rows > k
-        if (r0 && i0 > k) atomicMax(&s_key[(k + 1) & 1], pivot_key(v0, i0));
-        if (r1 && i1 > k) atomicMax(&s_key[(k + 1) & 1], pivot_key(v1, i1));
+      if (cand) {  // candidates for the next pivot: rows > k (one wavefront)
+        const unsigned c0 = (r0 && i0 > k) ? pivot_key(v0, i0) : 0u;
+        const unsigned c1 = (r1 && i1 > k) ? pivot_key(v1, i1) : 0u;
+        const unsigned m = wave_umax(c0 > c1 ? c0 : c1);
+        if (lane == 0) s_key[(k + 1) & 1] = m;
       }
       if (r0) col[i0] = v0;
       if (r1) col[i1] = v1;
