@@ -289,6 +289,37 @@ def test_workgroup_count_does_not_change_result(pk, wg):
     assert rel(u, ref) <= 1e-8
 
 
+@pytest.mark.parametrize("symmetric", [False, True])
+@pytest.mark.parametrize("wg", [3, 8, 37])
+def test_long_range_couplings_match_oracle(pk, symmetric, wg):
+    """Rows coupled across the whole index range: every workgroup's products
+    read rows owned by every other one (the neighbour waits span the team;
+    37 is not a multiple of 8, so slots equal ranks there)."""
+    say("long-range", "symmetric" if symmetric else "nonsymmetric", "workgroups", wg)
+    A = W.random_sparse(6000, 0.001, seed=21, symmetric=symmetric, shift=-4.0)
+    b = np.random.default_rng(6).standard_normal((A.shape[0], 2))
+    u, st = gpu_solve(pk, 0.6, A, b, tol=1e-9, workgroups=wg)
+    ref, _ = oracle.phipm(0.6, A, b, tol=1e-9)
+    assert st["status"] == 0 and st["workgroups"] == wg
+    assert st["lanczos"] == int(symmetric)
+    assert rel(u, ref) <= 1e-8
+
+
+def test_corner_coupling_matches_oracle(pk):
+    """A banded operator plus entries coupling the first and the last rows:
+    the first and last workgroups depend on the whole slot range."""
+    say("corner coupling")
+    A = W.convdiff2d(64, 20.0, 10.0)
+    n = A.shape[0]
+    A = sp.csr_matrix(A + sp.csr_matrix(([500.0, -300.0], ([0, n - 1], [n - 1, 0])), shape=(n, n)))
+    A.sort_indices()
+    b = np.random.default_rng(7).standard_normal((n, 3))
+    u, st = gpu_solve(pk, 2e-3, A, b, tol=1e-9, workgroups=4)
+    ref, _ = oracle.phipm(2e-3, A, b, tol=1e-9)
+    assert st["status"] == 0
+    assert rel(u, ref) <= 1e-8
+
+
 FP32_CASES = [
     # name, builder, p, t, tol
     ("config1 lap2d-30 p1", None, 1, 1e-3, 1e-7),
