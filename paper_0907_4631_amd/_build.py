@@ -24,6 +24,11 @@ FLAGS = [
     # per-lane LDS atomics (pivot search) stay per-lane instead of becoming a
     # scalar loop over the active lanes
     "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
+    # callers assume the calling convention's clobbers instead of the callee's
+    # actual register use: the persistent solver's register allocation (and
+    # speed) then does not shift with every change inside its out-of-line
+    # phases (the step decision, the proposer)
+    "-mllvm", "-enable-ipra=false",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -145,16 +145,28 @@ __device__ __forceinline__ unsigned wave_umax(unsigned v) {
   return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Gauss-Jordan elimination with [P | Q] by columns in LDS: P at M, Q at G
-// (both stride ld, lanes own rows i and i+64, wavefronts own columns, one
-// barrier per column; wavefront 0, which owns column k+1, posts the next
-// pivot as the wave-wide maximum of its candidates' pivot keys).
-__device__ __forceinline__ void gj_eliminate(int N, double* M, int ld, double* G, int ldq,
-                                             unsigned* s_key) {
-  const int tid = threadIdx.x;
-  const int lane = tid % WAVE, wv = tid / WAVE;
+// Gauss-Jordan elimination with P by columns in LDS (M, stride ld) and Q in
+// registers (N <= 128), so that LDS and vector ALU work side by side.  Lanes
+// own rows l and l+64 (the second half only when HI, i.e. N > 64).  P: the
+// columns right of k are split over the wavefronts and updated in LDS;
+// wavefront 0, which owns column k+1, posts the next pivot as the wave-wide
+// maximum of its candidates' pivot keys.  Q: wavefront wv owns columns wv,
+// wv+16, ... (at most 8) in registers and takes their pivot row and row k by
+// lane reads.  One barrier per column; every entry gets the same update
+// expression, the row exchange folded in.
+template <bool HI>
+__device__ __forceinline__ void gj_hybrid(int N, double* M, int ld, double* Q, unsigned* s_key) {
+  constexpr int SL = 2 * WAVE / NWAVES;  // Q columns per wavefront for N = 128
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
   const int i0 = lane, i1 = lane + WAVE;
-  const bool r0 = i0 < N, r1 = i1 < N;
+  const bool r0 = i0 < N, r1 = HI && i1 < N;
+  double x0[SL], x1[SL];
+#pragma unroll
+  for (int sl = 0; sl < SL; ++sl) {
+    const int c = wv + sl * NWAVES;
+    x0[sl] = (c < N && r0) ? Q[i0 * N + c] : 0.0;
+    x1[sl] = (c < N && r1) ? Q[i1 * N + c] : 0.0;
+  }
   for (int k = 0; k < N; ++k) {
     const int piv = 255 - (int)(s_key[k & 1] & 0xffu);
     const double* colk = M + k * ld;
@@ -180,87 +192,27 @@ __device__ __forceinline__ void gj_eliminate(int N, double* M, int ld, double* G
     };
 #pragma unroll 4
     for (int j = k + 1 + wv; j < N; j += NWAVES) update(M + j * ld, j == k + 1);
-#pragma unroll 4
-    for (int j = wv; j < N; j += NWAVES) update(G + j * ldq, false);
-    __syncthreads();
-  }
-}
-
-// Gauss-Jordan elimination with [P | Q] (N <= 128) held in registers:
-// wavefront wv owns columns wv, wv+16, ... of [P | Q] (at most 16), lane l
-// rows l and l+64 (the second half only when HI, i.e. N > 64).  In step k
-// the owner of column k copies it to LDS; after one barrier every wavefront
-// reads the pivot entry and the multipliers from there and takes the pivot
-// row and row k of its own columns with lane reads.  The update of an entry
-// is the same expression as in the LDS variant, so the result is identical.
-template <bool HI>
-__device__ __forceinline__ void gj_registers(int N, const double* P, double* Q) {
-  constexpr int SL = 2 * 2 * WAVE / NWAVES;  // columns per wavefront for N = 128
-  __shared__ double s_col[2][2 * WAVE];
-  __shared__ unsigned s_key[2];
-  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-  const int i0 = lane, i1 = lane + WAVE;
-  const bool r0 = i0 < N, r1 = HI && i1 < N;
-  double x0[SL], x1[SL];
-#pragma unroll
-  for (int sl = 0; sl < SL; ++sl) {
-    const int j = wv + sl * NWAVES;
-    const double* src = j < N ? P : Q;
-    const int c = j < N ? j : j - N;
-    x0[sl] = (j < 2 * N && r0) ? src[i0 * N + c] : 0.0;
-    x1[sl] = (j < 2 * N && r1) ? src[i1 * N + c] : 0.0;
-  }
-  if (wv == 0) {  // first pivot: column 0 (slot 0 of wavefront 0)
-    const unsigned c0 = r0 ? pivot_key(x0[0], i0) : 0u;
-    const unsigned c1 = r1 ? pivot_key(x1[0], i1) : 0u;
-    const unsigned m = wave_umax(c0 > c1 ? c0 : c1);
-    if (lane == 0) s_key[0] = m;
-  }
-  for (int k = 0; k < N; ++k) {
-    const int buf = k & 1;
-    if (wv == k % NWAVES) {
-      const int ks = k / NWAVES;
-#pragma unroll
-      for (int sl = 0; sl < SL; ++sl)
-        if (sl == ks) {
-          if (r0) s_col[buf][i0] = x0[sl];
-          if (r1) s_col[buf][i1] = x1[sl];
-        }
-    }
-    __syncthreads();
-    const int piv = 255 - (int)(s_key[buf] & 0xffu);
-    const double* colk = s_col[buf];
-    const double inv = 1.0 / colk[piv];
-    const double kk = colk[k];
-    const double f0 = r0 ? colk[i0] : 0.0;
-    const double f1 = r1 ? colk[i1] : 0.0;
     const int pl = piv % WAVE, kl = k % WAVE;
     const bool phi = piv >= WAVE, khi = k >= WAVE;
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
-      const int j = wv + sl * NWAVES;
-      if (j > k && j < 2 * N) {
+      if (wv + sl * NWAVES < N) {
         const double pr = lane_value(HI && phi ? x1[sl] : x0[sl], pl) * inv;
         const double kj = lane_value(HI && khi ? x1[sl] : x0[sl], kl);
         const double v0 = i0 == k ? pr : (i0 == piv ? kj - kk * pr : x0[sl] - f0 * pr);
         const double v1 = i1 == k ? pr : (i1 == piv ? kj - kk * pr : x1[sl] - f1 * pr);
-        if (j == k + 1) {  // candidates for the next pivot: rows > k
-          const unsigned c0 = (r0 && i0 > k) ? pivot_key(v0, i0) : 0u;
-          const unsigned c1 = (r1 && i1 > k) ? pivot_key(v1, i1) : 0u;
-          const unsigned m = wave_umax(c0 > c1 ? c0 : c1);
-          if (lane == 0) s_key[(k + 1) & 1] = m;
-        }
         if (r0) x0[sl] = v0;
         if (HI && r1) x1[sl] = v1;
       }
     }
+    __syncthreads();
   }
 #pragma unroll
   for (int sl = 0; sl < SL; ++sl) {
-    const int j = wv + sl * NWAVES;
-    if (j >= N && j < 2 * N) {
-      if (r0) Q[i0 * N + (j - N)] = x0[sl];
-      if (r1) Q[i1 * N + (j - N)] = x1[sl];
+    const int c = wv + sl * NWAVES;
+    if (c < N) {
+      if (r0) Q[i0 * N + c] = x0[sl];
+      if (r1) Q[i1 * N + c] = x1[sl];
     }
   }
   __syncthreads();
@@ -270,34 +222,26 @@ __device__ __forceinline__ void gj_registers(int N, const double* P, double* Q) 
 // partial pivoting (P, Q row-major N x N in device memory).  Pivots are
 // chosen with pivot keys, ties to the smallest row; the row exchange is
 // folded into the update of each column (row k takes the scaled pivot row,
-// the pivot row takes the eliminated old row k).  N <= 128: the system in
-// LDS while [P | Q] fits there (N <= 92), else N <= 128: in registers
-// (gj_registers, faster than LDS from about N = 100), larger N: in device
-// memory.  L: DENSE_LDS doubles of shared memory; Wk is not used.
+// the pivot row takes the eliminated old row k).  N <= 128: P by columns in
+// LDS and Q in registers (gj_hybrid); larger N: in device memory.  L:
+// DENSE_LDS doubles of shared memory; Wk is not used.
 __device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q, double* L,
                                                 double* Wk) {
   const int tid = threadIdx.x;
   const int ld = (N + 1) & ~1;  // column stride of the transposed system in LDS
-  if (2 * N * ld <= DENSE_LDS) {
-    // [P | Q] by columns in LDS (up to N = 92)
+  if (N <= 2 * WAVE) {
     __shared__ unsigned s_key[2];
     double* M = L;  // P stored by columns: entry (i, j) at M[j * ld + i]
     if (tid == 0) { s_key[0] = 0u; s_key[1] = 0u; }
     for (int e = tid; e < N * N; e += BLOCK) {
       const int i = e / N, j = e - i * N;
       M[j * ld + i] = P[e];
-      L[N * ld + j * ld + i] = Q[e];
     }
     __syncthreads();
     for (int i = tid; i < N; i += BLOCK) atomicMax(&s_key[0], pivot_key(M[i], i));
     __syncthreads();
-    gj_eliminate(N, M, ld, L + N * ld, ld, s_key);
-    for (int e = tid; e < N * N; e += BLOCK) Q[e] = L[N * ld + (e % N) * ld + e / N];
-    __syncthreads();
-    return;
-  }
-  if (N <= 2 * WAVE) {
-    gj_registers<true>(N, P, Q);
+    if (N <= WAVE) gj_hybrid<false>(N, M, ld, Q, s_key);
+    else gj_hybrid<true>(N, M, ld, Q, s_key);
     return;
   }
   __shared__ int s_pivg;
