@@ -25,18 +25,21 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per solver launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE
 # (scaled against a plain device copy), keyed by workload and by the hash of
-# the kernel sources they were measured on; reported only while that hash
+# the kernel sources and build script they were measured on; reported only while that hash
 # still matches (the summaries with their commands are under profiles/).
 MEASURED_TRAFFIC = {
-    "convdiff2d-512": ("1f01297daa57f943", 447716888217.0),
+    "convdiff2d-512": ("995c959f46ba553c", 435754174493.0),
 }
 
 
 def kernel_source_hash() -> str:
+    """sha256[:16] of the kernel sources and the build script (its flags)."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_0907_4631_amd", "csrc", "*"))):
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_0907_4631_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "paper_0907_4631_amd", "_build.py"))
+    for f in files:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
