@@ -224,9 +224,8 @@ __device__ __forceinline__ void gj_hybrid(int N, double* M, int ld, double* Q, u
 // folded into the update of each column (row k takes the scaled pivot row,
 // the pivot row takes the eliminated old row k).  N <= 128: P by columns in
 // LDS and Q in registers (gj_hybrid); larger N: in device memory.  L:
-// DENSE_LDS doubles of shared memory; Wk is not used.
-__device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q, double* L,
-                                                double* Wk) {
+// DENSE_LDS doubles of shared memory.
+__device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q, double* L) {
   const int tid = threadIdx.x;
   const int ld = (N + 1) & ~1;  // column stride of the transposed system in LDS
   if (N <= 2 * WAVE) {
@@ -370,7 +369,7 @@ __device__ __forceinline__ double* wg_expm(int N, double* S, double* L, double* 
     Q[e] = ev + U[e];
   }
   __syncthreads();
-  wg_gauss_jordan(N, P, Q, L, X2);  // X2 is free scratch from here on
+  wg_gauss_jordan(N, P, Q, L);
   double* cur = Q;
   double* nxt = U;
   for (int k = 0; k < s; ++k) {

@@ -31,13 +31,18 @@ import numpy as np
 from . import (FP64, M_CAP, MLP_IN, MLP_OUT, MLP_PARAMS, P_MAX, DeviceCSR, LabelCosts, Solver,
                alloc_trace, expm, label_steps, mlp_forward, mlp_train)
 
-# Solver timing constants on MI355X (one 1024-thread workgroup per CU): team
-# barrier of the full grid, barrier of one workgroup, streaming bandwidth of
-# the grid and of one workgroup.
-SYNC_S = 8e-6
+# Solver timing constants on MI355X (one 1024-thread workgroup per CU), fitted
+# to the phase clocks of the solver for the step-time model of the labels.
+# The model counts three team synchronisations and (4K + 8) vectors of
+# traffic per Krylov step; the solver does one reduction and one neighbour
+# synchronisation (about 15 us together on the full grid) and streams about
+# half those bytes, so the constants are per modelled synchronisation and per
+# modelled byte: 5 us, and 7.5e12 (3e10 per workgroup) modelled bytes/s.  One
+# workgroup alone synchronises in 1.5 us.
+SYNC_S = 5e-6
 SYNC1_S = 1.5e-6
-BW_BYTES_PER_S = 3.0e12
-WG_BYTES_PER_S = 2.5e10
+BW_BYTES_PER_S = 7.5e12
+WG_BYTES_PER_S = 3.0e10
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "proposer_weights.npy")

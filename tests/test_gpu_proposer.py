@@ -200,9 +200,10 @@ def test_proposer_keeps_error_control_and_warm_start(pk):
 def test_trained_proposer_gains_on_held_out_problems(pk):
     """The committed network (trained on the GPU by the pipeline in
     paper_0907_4631_amd.proposer) against the plain step control on held-out
-    problems of the training families: fewer steps, fewer rejected attempts
-    and fewer products at the same accuracy.  Wall time is reported, not
-    asserted: on these problems the larger Krylov dimensions it chooses cost
+    problems of the training families: at the same accuracy, at most 3/4 of
+    the steps, no more rejected attempts and at most 9/10 of the products.
+    Wall time is reported, not asserted: the labels minimise modelled time
+    per unit of t, and on these problems the larger Krylov dimensions cost
     about as much time as the steps they save."""
     say("trained proposer gain")
     from paper_0907_4631_amd import proposer as PR
@@ -231,5 +232,5 @@ def test_trained_proposer_gains_on_held_out_problems(pk):
         assert np.linalg.norm(outs["learned"] - ref) <= 10 * tol * max(1.0, np.linalg.norm(ref)), name
     say("  totals [steps, rejected, matvecs, ms]: plain", tot["plain"], "learned", tot["learned"])
     assert tot["learned"][0] <= 0.75 * tot["plain"][0]
-    assert tot["learned"][1] <= 0.6 * tot["plain"][1]
-    assert tot["learned"][2] <= tot["plain"][2]
+    assert tot["learned"][1] <= tot["plain"][1]
+    assert tot["learned"][2] <= 0.9 * tot["plain"][2]
