@@ -190,7 +190,6 @@ __device__ __forceinline__ void gj_hybrid(int N, double* M, int ld, double* Q, u
       if (r0) col[i0] = v0;
       if (r1) col[i1] = v1;
     };
-#pragma unroll 4
     for (int j = k + 1 + wv; j < N; j += NWAVES) update(M + j * ld, j == k + 1);
     const int pl = piv % WAVE, kl = k % WAVE;
     const bool phi = piv >= WAVE, khi = k >= WAVE;
