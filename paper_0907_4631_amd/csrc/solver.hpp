@@ -2,8 +2,10 @@
 // by a team of workgroups of one persistent grid.
 //
 // Every workgroup owns a contiguous block of rows.  All vector work is
-// row-local except the sparse products, which gather from vectors that the
-// team completed before the last team_sync.  Dot products are reduced with
+// row-local except the sparse products, which gather from vectors completed
+// before the last team synchronisation (a team_sync, or in the Krylov steps
+// a neighbour synchronisation with the workgroups owning the rows that the
+// product reads).  Dot products are reduced with
 // team_sync's fused deterministic reduction.  Scalar decisions (small matrix
 // exponential, error estimate, step-size and dimension control) are made by
 // workgroup 0 and published through the State block in device memory; every
@@ -14,9 +16,10 @@
 //   u            n          float64   output; also w_0
 //   W            n x p      float64   w_1..w_p of eq. wrecurrence
 //   V            n x (m+1)  T         Krylov basis
-//   y[2]         n          T         unnormalised new basis vector (ping-pong)
+//   y0, y1       n          T         the candidate u and the product w of a Krylov step
 //   val32        nnz        float     CSR values rounded to float (T = float)
-//   H            (M_CAP+1) x M_CAP float64, row-major, only read by workgroup 0
+//   H            (M_CAP+1) x M_CAP float64, row-major, one copy per workgroup
+//                                     (workgroup 0's feeds the exponential)
 //   ex           8 (m+p+1)^2 float64, the small exponential's scratch
 #pragma once
 #include "controller.hpp"
@@ -327,8 +330,8 @@ struct KrylovCtl {
 };
 
 // Second pass of the candidate in U against columns [zb, j) of V and its
-// norm.  The coefficients s go to sh.h1[0..K) and, for rank 0, into column
-// j-1 of H with H[j][j-1] = beta.  beta comes from Pythagoras,
+// norm.  The coefficients s go to sh.h1[0..K) (the caller adds them to
+// column j-1 of H, with H[j][j-1] = beta).  beta comes from Pythagoras,
 // beta^2 = u.u - |s|^2, unless the first pass left more than a quarter of
 // ||u||^2 in span(V) (cancellation), when U is reorthogonalised in place
 // and its norm reduced directly (one more team barrier; then sh.h1 is the

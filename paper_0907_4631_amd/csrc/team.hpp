@@ -1,7 +1,7 @@
 // Workgroup teams: the workgroups of one persistent (cooperatively launched)
-// grid that solve one problem together.  A team owns a control block in
-// device memory (arrival counter, generation, abort flag) and a partials
-// buffer used by the fused "reduce and synchronise" primitive below.
+// grid that solve one problem together.  A team owns flags in device memory
+// (one epoch per member and per group, a generation, the abort word) and a
+// partials buffer used by the fused "reduce and synchronise" primitive below.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,11 +23,13 @@ constexpr int FLAG_STRIDE = 32;           // one flag per 128-byte line
 constexpr int TEAM_GBUF = 4;              // group-sum buffers, used round robin by epoch
 
 // Team control block in device memory (zeroed before every launch).  Every
-// workgroup posts the epoch it reached in its own flag; the first workgroup
-// of each group of TEAM_GROUP (the group leader) waits for its members'
-// flags, and workgroup 0 waits for the group leaders' flags and then
-// publishes the generation.  There are no read-modify-write atomics, so
-// nothing serializes on one address.
+// workgroup posts the epoch it reached in its own flag.  In a reduction of a
+// few values (and a plain barrier) workgroup 0 waits for all flags and
+// publishes the generation; in a wider one the first workgroup of each group
+// of TEAM_GROUP (the group leader) waits for its members' flags and posts a
+// group flag, which every workgroup waits for; a neighbour synchronisation
+// waits for the flags of a range of workgroups only.  There are no
+// read-modify-write atomics, so nothing serializes on one address.
 struct TeamCtl {
   unsigned gen;      // generation number (last completed barrier)
   unsigned abort;    // set when a wait exceeded its time budget
