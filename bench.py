@@ -267,6 +267,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
                     help="basis precision (default: the workload's)")
     ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the autotuner")
+    ap.add_argument("--fixed-m", type=int, default=0, metavar="M",
+                    help="single solves: the paper's phip (Krylov dimension fixed at M, only tau "
+                         "adapted) instead of phipm")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (3 times), so that "
                          "HBM byte counters can be scaled against a known transfer")
@@ -303,8 +306,11 @@ def main():
     b = torch.as_tensor(np.ascontiguousarray(pb.b.T), device="cuda")
     u = torch.empty(pb.n, dtype=torch.float64, device="cuda")
     precision = pk.FP32_BASIS if args.precision == "fp32" else pk.FP64
+    kw = {}
+    if args.fixed_m > 0:
+        kw = dict(adapt_m=0, m_init=args.fixed_m, m_max=args.fixed_m)
     solver = pk.Solver(A, pb.p, tol=pb.tol, precision=precision, workgroups=args.workgroups,
-                       validate=1)
+                       validate=1, **kw)
     st = None
     for _ in range(max(1, args.warmup)):
         st = solver(pb.t, b, u, stats=True)
@@ -349,6 +355,7 @@ def main():
             "workload": WORKLOADS[args.workload][1],
             "n": pb.n, "nnz": int(pb.A.nnz), "p": pb.p, "t": pb.t, "tol": pb.tol,
             "workgroups": st["workgroups"], "lanczos": st["lanczos"],
+            "method": f"phip (m fixed at {args.fixed_m})" if args.fixed_m > 0 else "phipm",
             "solve_stats": {k: st[k] for k in ("steps", "rejected", "matvecs", "expms",
                                                 "m_last", "fp64_fallback",
                                                 "fp32_error_estimate")},

@@ -289,6 +289,26 @@ def test_workgroup_count_does_not_change_result(pk, wg):
     assert rel(u, ref) <= 1e-8
 
 
+@pytest.mark.parametrize("name,build,p,t,tol,m", [
+    ("lap2d-50 p1 m30", lambda: W.laplace2d(50), 1, 2e-3, 1e-8, 30),
+    ("convdiff-64 p2 m30", lambda: W.convdiff2d(64, 30.0, 30.0), 2, 5e-3, 1e-8, 30),
+    ("convdiff-48 p0 m8", lambda: W.convdiff2d(48, 40.0, 20.0), 0, 5e-3, 1e-7, 8),
+])
+def test_fixed_m_phip_matches_oracle(pk, name, build, p, t, tol, m):
+    """The paper's phip: Krylov dimension fixed, only the step size adapted
+    (Algorithm 4 without its m branch)."""
+    say("phip case", name)
+    A = build()
+    b = np.random.default_rng(8).standard_normal((A.shape[0], p + 1))
+    kw = dict(tol=tol, adapt_m=0, m_init=m, m_max=m)
+    u, st = gpu_solve(pk, t, A, b, **kw)
+    ref, ost = oracle.phipm(t, A, b, **kw)
+    say("  gpu", st, "\n  oracle", ost)
+    assert st["status"] == 0
+    assert st["m_last"] == m
+    assert rel(u, ref) <= 10 * tol
+
+
 @pytest.mark.parametrize("symmetric", [False, True])
 @pytest.mark.parametrize("wg", [3, 8, 37])
 def test_long_range_couplings_match_oracle(pk, symmetric, wg):
