@@ -56,6 +56,9 @@ WORKLOADS = {
                               "(Laplacian + diag(1 - 3 u^2), n=1048576), p=2, t=1e-3, tol=1e-6, "
                               "successive calls with new b; learned (tau, m) proposer vs plain "
                               "step control (cold and warm start)", "fp64"),
+    "heston-100x51": ("heston_problem", "finite-difference Heston operator on the 100x51 grid "
+                      "of the paper's Sect. 5.1 (n=5100), p=1, t=T=1, tol=1e-6, Arnoldi, FP64",
+                      "fp64"),
     "convdiff2d-batch256": ("config4", "256 independent 2D upwind convection-diffusion solves "
                             "(N_i in 32..256, Peclet in 0..100, p_i in 0..3, t_i in 1e-4..1e-1, "
                             "tol=1e-7) in one persistent autotuned launch replayed from a hipGraph",

@@ -289,6 +289,19 @@ def test_workgroup_count_does_not_change_result(pk, wg):
     assert rel(u, ref) <= 1e-8
 
 
+@pytest.mark.parametrize("tol", [1e-4, 1e-6])
+def test_heston_matches_oracle(pk, tol):
+    """The paper's Heston example (n = 5100, p = 1, t = T = 1) in the
+    benchmark's launch configuration."""
+    say("heston tol", tol)
+    pb = W.heston_problem(tol)
+    u, st = gpu_solve(pk, pb.t, pb.A, pb.b, tol=tol)
+    ref, ost = oracle.phipm(pb.t, pb.A, pb.b, tol=tol)
+    say("  gpu", st, "\n  oracle", ost)
+    assert st["status"] == 0 and st["lanczos"] == 0
+    assert np.linalg.norm(u - ref) <= 10 * tol * max(1.0, np.linalg.norm(ref))
+
+
 @pytest.mark.parametrize("name,build,p,t,tol,m", [
     ("lap2d-50 p1 m30", lambda: W.laplace2d(50), 1, 2e-3, 1e-8, 30),
     ("convdiff-64 p2 m30", lambda: W.convdiff2d(64, 30.0, 30.0), 2, 5e-3, 1e-8, 30),

@@ -458,3 +458,21 @@ def test_corrector_improves_fixed_steps(oracle_lib, p):
         assert st["steps"] == 6
         errs.append(np.linalg.norm(u - ref))
     assert errs[0] < 0.5 * errs[1], errs
+
+
+def test_heston_operator_is_exact_for_linear_prices():
+    """The Heston discretisation (workloads.heston) with its boundary vector:
+    for U = s every difference quotient is exact (U_s = 1, U_ss = U_v = U_vv =
+    U_sv = 0) and the boundary values (U(0, v) = 0, U(s, V) = s, U_s(S, v) = 1)
+    agree with U, so A s + b1 = (rd - rf) s - rd s = -rf s."""
+    import workloads as W
+    for rf in (0.0, 0.01):
+        A, b0, b1 = W.heston(rf=rf)
+        ds = 800.0 / 101
+        s = np.tile(np.arange(1, 101) * ds, 51)
+        r = A @ s + b1
+        assert np.abs(r + rf * s).max() <= 1e-12 * np.abs(A @ s).max()
+    # structure: 100 x 51 unknowns, the v = 0 line with the one-sided U_v
+    assert A.shape == (5100, 5100)
+    assert A.nnz == 44900
+    assert np.all(b0[:12] == 0.0) and b0[12] == pytest.approx(13 * ds - 100.0)

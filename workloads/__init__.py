@@ -122,6 +122,78 @@ def sine_mode2d(N: int, k1: int, k2: int) -> tuple[np.ndarray, float]:
     return v / np.linalg.norm(v), lam
 
 
+def heston(Ns: int = 100, Nv: int = 51, K: float = 100.0, S: float = 800.0, V: float = 5.0,
+           kappa: float = 2.0, eta: float = 0.2, lam: float = 0.3, rho: float = 0.8,
+           rd: float = 0.03, rf: float = 0.0):
+    """Finite-difference Heston operator of the paper's Sect. 5.1: u' = A u + b1,
+    u(0) = b0 (the call payoff).
+
+    Grid: s_i = i ds (i = 1..Ns, ds = S/(Ns+1)) and v_j = j dv (j = 0..Nv-1,
+    dv = V/Nv): v = 0 is a grid line, s = 0, s = S and v = V are not.  Unknown
+    (i, j) has index (i-1) + Ns j.  Central second-order differences in the
+    interior (the cross derivative by its four diagonal neighbours); on v = 0
+    the boundary equation U_t = (rd - rf) s U_s + kappa eta U_v - rd U with
+    the one-sided three-point U_v.  Boundary values: U(0, v) = 0, U(s, V) = s,
+    and U(S, v) = U(s_Ns, v) + ds (the first-order form of U_s(S, v) = 1);
+    known values go into b1.  Returns (A, b0, b1)."""
+    ds = S / (Ns + 1)
+    dv = V / Nv
+    n = Ns * Nv
+    rows, cols, vals = [], [], []
+    b1 = np.zeros(n)
+
+    def idx(i, j):
+        return (i - 1) + Ns * j
+
+    def add(k, i, j, c, s_i):
+        # coefficient c on U(s_i, v_j); points off the grid are boundary values
+        if c == 0.0:
+            return
+        if i == 0:                       # U(0, v) = 0
+            return
+        if j == Nv:                      # U(s, V) = s
+            b1[k] += c * (i * ds if i <= Ns else S)
+            return
+        if i == Ns + 1:                  # U(S, v) = U(s_Ns, v) + ds
+            rows.append(k); cols.append(idx(Ns, j)); vals.append(c)
+            b1[k] += c * ds
+            return
+        rows.append(k); cols.append(idx(i, j)); vals.append(c)
+
+    for j in range(Nv):
+        v = j * dv
+        for i in range(1, Ns + 1):
+            s = i * ds
+            k = idx(i, j)
+            if j == 0:
+                cs = (rd - rf) * s / (2 * ds)
+                cv = kappa * eta / (2 * dv)
+                add(k, i + 1, 0, cs, s)
+                add(k, i - 1, 0, -cs, s)
+                add(k, i, 0, -3 * cv - rd, s)
+                add(k, i, 1, 4 * cv, s)
+                add(k, i, 2, -cv, s)
+                continue
+            a_ss = 0.5 * v * s * s / (ds * ds)
+            a_vv = 0.5 * lam * lam * v / (dv * dv)
+            a_s = (rd - rf) * s / (2 * ds)
+            a_v = kappa * (eta - v) / (2 * dv)
+            a_sv = rho * lam * v * s / (4 * ds * dv)
+            add(k, i, j, -2 * a_ss - 2 * a_vv - rd, s)
+            add(k, i + 1, j, a_ss + a_s, s)
+            add(k, i - 1, j, a_ss - a_s, s)
+            add(k, i, j + 1, a_vv + a_v, s)
+            add(k, i, j - 1, a_vv - a_v, s)
+            add(k, i + 1, j + 1, a_sv, s)
+            add(k, i - 1, j - 1, a_sv, s)
+            add(k, i - 1, j + 1, -a_sv, s)
+            add(k, i + 1, j - 1, -a_sv, s)
+    A = _csr(np.array(rows), np.array(cols), np.array(vals), n)
+    s_of = np.tile(np.arange(1, Ns + 1) * ds, Nv)
+    b0 = np.maximum(s_of - K, 0.0)
+    return A, b0, b1
+
+
 # ------------------------------------------------------------------ configs
 
 @dataclasses.dataclass
@@ -165,6 +237,13 @@ def config3() -> Problem:
     g = rng(3000)
     b = g.uniform(-1.0, 1.0, size=(A.shape[0], 4))
     return Problem("laplace3d-128^3-p3", A, b, 1e-4, 1e-6, True, fp32_basis=True)
+
+
+def heston_problem(tol: float = 1e-6) -> Problem:
+    """The paper's Heston example: u(1) = exp(A) b0 + phi_1(A) b1 on the 100 x 51
+    grid (p = 1, t = T = 1)."""
+    A, b0, b1 = heston()
+    return Problem("heston-100x51", A, np.stack([b0, b1], axis=1), 1.0, tol, False)
 
 
 def config5_matrix() -> sp.csr_matrix:
