@@ -74,7 +74,8 @@ typedef struct {
   int32_t corrector;     /* 1: eq. phipapprox2 (default); 0: eq. phipapprox */
   double tau_fixed;      /* > 0: fixed substep, every attempt accepted (diagnostics) */
   int64_t max_attempts;  /* limit on attempts (accepted + rejected); default 1e6 */
-  int32_t workgroups;    /* 0: library choice; else workgroups cooperating on the solve */
+  int32_t workgroups;    /* 0: library choice (1 up to 2048 rows, else one per 320 rows,
+                            at most one per CU); else workgroups cooperating on the solve */
   int32_t validate;      /* 1 (default): check CSR structure and finiteness on the device */
   const float* proposer; /* device, PHIPM_MLP_PARAMS floats: learned (tau, m) proposer that
                             seeds every step (see phipm_mlp_*); NULL (default): plain
