@@ -56,6 +56,11 @@ WORKLOADS = {
                               "(Laplacian + diag(1 - 3 u^2), n=1048576), p=2, t=1e-3, tol=1e-6, "
                               "successive calls with new b; learned (tau, m) proposer vs plain "
                               "step control (cold and warm start)", "fp64"),
+    "allencahn-1024-ere": ("config5", "Allen-Cahn u_t = Lap u + u - u^3 on the 1024x1024 grid "
+                           "(n=1048576) from the config-5 field, exponential Rosenbrock-Euler "
+                           "steps h=1e-3, one phipm call per step (p=1, tol=1e-6, Lanczos); "
+                           "learned (tau, m) proposer vs plain step control (cold and warm)",
+                           "fp64"),
     "heston-100x51": ("heston_problem", "finite-difference Heston operator on the 100x51 grid "
                       "of the paper's Sect. 5.1 (n=5100), p=1, t=T=1, tol=1e-6, Arnoldi, FP64",
                       "fp64"),
@@ -116,6 +121,61 @@ def cpu_baseline_batch(probs, gpu_stats, budget_s=20.0, seed=7):
             "kind": "oracle",
             "sample": f"{done} randomly chosen of the {len(probs)} instances ({spent:.1f} s), "
                       f"scaled to the batch by rows x products"}
+
+
+def run_integrator(args):
+    """Exponential Rosenbrock-Euler steps of the Allen-Cahn equation whose
+    Jacobians the call sequence samples: the learned proposer (the timed
+    variant) beside the plain step control cold and warm-started."""
+    import torch
+    import paper_0907_4631_amd as pk
+    from paper_0907_4631_amd import integrator
+    from paper_0907_4631_amd import proposer as PR
+    import workloads as W
+    N, h, tol, steps = 1024, 1e-3, 1e-6, args.steps
+    lap = W.laplace2d(N)
+    u0 = W.smooth_field(N, 5999)
+    res, outs = {}, {}
+    for name in ("learned", "plain-cold", "plain-warm"):
+        kw = {"proposer": PR.load()} if name == "learned" else {"warm": name == "plain-warm"}
+        ig = integrator.AllenCahnERE(lap, u0, h, tol=tol, **kw)
+        sts = ig.run(max(1, args.warmup), stats=True)        # untimed, then restart from u0
+        ig.u.copy_(torch.as_tensor(u0, device="cuda"))
+        if ig.hist is not None:
+            ig.hist.zero_()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ig.run(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        if pk.lib().phipm_last_status() != 0:
+            raise pk.PhipmError(pk.lib().phipm_last_status(), name)
+        outs[name] = ig.u.cpu().numpy()
+        ig.u.copy_(torch.as_tensor(u0, device="cuda"))   # statistics from an untimed repeat
+        if ig.hist is not None:
+            ig.hist.zero_()
+        sts = ig.run(steps, stats=True)
+        res[name] = {"ms_per_step": ms, "steps_per_s": 1e3 / ms,
+                     "solver_steps": sum(x["steps"] for x in sts),
+                     "rejected": sum(x["rejected"] for x in sts),
+                     "matvecs": sum(x["matvecs"] for x in sts)}
+    ref = outs["plain-cold"]
+    for name in res:
+        res[name]["max_diff_vs_plain_cold"] = float(np.linalg.norm(outs[name] - ref) /
+                                                    max(1.0, np.linalg.norm(ref)))
+    ms = res["learned"]["ms_per_step"]
+    line = {
+        "metric": "phipm solves/s (adaptive Krylov phi-function solve to t_end) and HBM GB/s",
+        "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["allencahn-1024-ere"][1], "n": N * N, "h": h,
+                   "integrator_steps": steps, "variants": res},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def run_calls(args):
@@ -303,6 +363,9 @@ def main():
         return
     if args.workload == "reaction2d-1024-calls":
         run_calls(args)
+        return
+    if args.workload == "allencahn-1024-ere":
+        run_integrator(args)
         return
     pb = build_problem(args.workload)
     A = pk.DeviceCSR(pb.A, device="cuda")
