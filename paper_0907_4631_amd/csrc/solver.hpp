@@ -197,10 +197,9 @@ __device__ __forceinline__ SpmvSmem<float>& smem_for<float>(Shared& sh) { return
 // 64-row chunks, so many independent loads are in flight; u and w are
 // re-read from L1.  With more jobs than half the wavefronts and at most one
 // row per thread, u and w are staged in LDS instead and each wavefront
-// streams its columns with eight loads in flight per lane (the same per-job
-// row order).  Partial
-// sums are reduced with DPP and then across a job's wavefronts in a fixed
-// order.
+// streams its columns with up to sixteen loads in flight per lane (the same
+// per-job row order).  Partial sums are reduced with DPP and then across a
+// job's wavefronts in a fixed order.
 template <typename T>
 __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, int K, const T* U,
                                             const T* Wv, bool with_u, int rb, int re,
@@ -215,7 +214,7 @@ __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, i
   if (wpj == 1 && re - rb <= BLOCK) {
     // more jobs than half the wavefronts and one row per thread: u and w
     // are staged in LDS, and wavefront wv takes jobs wv, wv+16, ..., one per
-    // pass over the rows with eight rows of a lane loaded together, so its
+    // pass over the rows with all rows of a lane loaded together, so its
     // global loads are basis columns only (per job the same row order as the
     // path below)
     constexpr int JC = 1;  // jobs per pass over the rows
@@ -228,7 +227,7 @@ __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, i
     }
     __syncthreads();
     const int nj = wv < jobs ? (jobs - wv + NWAVES - 1) / NWAVES : 0;
-    constexpr int RR = 8;  // rows per lane and iteration
+    constexpr int RR = 16;  // rows per lane and iteration (all of them: rows <= BLOCK)
     for (int t0 = 0; t0 < nj; t0 += JC) {
       // a_t = sum v.w and b_t = sum v.u over the rows; the (u.u, u.w) job
       // reads u as its column, so a = u.w and b = u.u there.  Slots past
