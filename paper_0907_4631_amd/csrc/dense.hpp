@@ -299,12 +299,42 @@ __device__ __forceinline__ void wg_gauss_jordan(int N, double* P, double* Q, dou
   }
 }
 
+// C[:, c] = A B[:, c] for the two columns c0 and c1 of N x N row-major
+// matrices (every row of those two columns; the rest of C is not written).
+// The columns of B are staged in LDS; eight consecutive lanes share one
+// output entry and add their partial sums with shuffles.
+__device__ __forceinline__ void wg_matcols(int N, const double* __restrict__ A,
+                                           const double* __restrict__ B, double* __restrict__ C,
+                                           int c0, int c1, double* L) {
+  for (int e = threadIdx.x; e < 2 * N; e += BLOCK)
+    L[e] = B[(e < N ? e : e - N) * N + (e < N ? c0 : c1)];
+  __syncthreads();
+  for (int t0 = 0; t0 < 16 * N; t0 += BLOCK) {  // same trip count on every lane
+    const int t = t0 + threadIdx.x;
+    const int o = t >> 3, q = t & 7;
+    const bool valid = o < 2 * N;
+    const int i = valid ? (o < N ? o : o - N) : 0;
+    const double* col = L + (o < N ? 0 : N);
+    double acc = 0.0;
+    if (valid)
+      for (int j = q; j < N; j += 8) acc = fma(A[i * N + j], col[j], acc);
+    acc += __shfl_xor(acc, 1, WAVE);
+    acc += __shfl_xor(acc, 2, WAVE);
+    acc += __shfl_xor(acc, 4, WAVE);
+    if (valid && q == 0) C[i * N + (o < N ? c0 : c1)] = acc;
+  }
+  __syncthreads();
+}
+
 // E = exp(A) for the N x N matrix in S[0] (overwritten).  S must hold 8
 // matrices of N*N doubles; L is DENSE_LDS doubles of shared memory.  Returns
 // (in shared out_*) the 1-norm of A and the number of squarings.  The result
-// is in the returned pointer (inside S).
+// is in the returned pointer (inside S).  With c0, c1 >= 0 only columns c0
+// and c1 of the result are valid: the last squaring then multiplies by those
+// two columns alone, since the solver reads nothing else of the exponential
+// (the saving the paper points out for the last column in Sect. 3.1).
 __device__ __forceinline__ double* wg_expm(int N, double* S, double* L, double* out_norm1,
-                                           int* out_s) {
+                                           int* out_s, int c0 = -1, int c1 = -1) {
   __shared__ double s_norm;
   __shared__ double s_c[14];
   const int tid = threadIdx.x;
@@ -371,8 +401,10 @@ __device__ __forceinline__ double* wg_expm(int N, double* S, double* L, double* 
   wg_gauss_jordan(N, P, Q, L);
   double* cur = Q;
   double* nxt = U;
+  const bool cols = c0 >= 0 && c1 >= 0;
   for (int k = 0; k < s; ++k) {
-    wg_matmul(N, cur, cur, nxt, L);
+    if (cols && k == s - 1) wg_matcols(N, cur, cur, nxt, c0, c1, L);
+    else wg_matmul(N, cur, cur, nxt, L);
     double* t = cur; cur = nxt; nxt = t;
   }
   if (tid == 0) { *out_norm1 = nrm; *out_s = s; }

@@ -225,7 +225,7 @@ __device__ double label_omega(const TraceStep& r, int mm, double tau, double* ex
     ex[e] = v;
   }
   __syncthreads();
-  const double* E = wg_expm(N, ex, L, &s_norm, &s_sq);
+  const double* E = wg_expm(N, ex, L, &s_norm, &s_sq, mm + p, mm + p);
   if (threadIdx.x == 0) s_c = E[(size_t)(mm - 1) * N + mm + p];
   __syncthreads();
   *knorm = s_norm;

@@ -637,8 +637,8 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       K[e] = v;
     }
     __syncthreads();
-    const double* E = wg_expm(N, ex, L, &s_norm, &s_sq);
     const int col = p == 0 ? 0 : m_use + p - 1;
+    const double* E = wg_expm(N, ex, L, &s_norm, &s_sq, col, m_use + p);
     for (int k = threadIdx.x; k < m_use; k += BLOCK) st->yb[k] = beta * E[(long long)k * N + col];
     if (threadIdx.x == 0) s_c = E[(long long)(m_use - 1) * N + m_use + p];
     __syncthreads();

@@ -133,6 +133,9 @@ FIXED = [
     ("lap2d-30 p1", lambda: W.laplace2d(30), 1, 1e-3, 1e-4, 12),
     ("convdiff-64 p3", lambda: W.convdiff2d(64, 30.0, 30.0), 3, 1e-3, 2.5e-4, 20),
     ("ragged-3000 p0", lambda: ragged_matrix(3000, 7) * 0.05, 0, 0.3, 0.1, 15),
+    # ||tau H^||_1 of about 20: two squarings, the last one by columns only
+    ("convdiff-64 p0 squarings", lambda: W.convdiff2d(64, 30.0, 30.0), 0, 2e-3, 1e-3, 20),
+    ("lap2d-30 p2 squarings", lambda: W.laplace2d(30), 2, 4e-3, 2e-3, 16),
 ]
 
 
