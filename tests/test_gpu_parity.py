@@ -136,6 +136,8 @@ FIXED = [
     # ||tau H^||_1 of about 20: two squarings, the last one by columns only
     ("convdiff-64 p0 squarings", lambda: W.convdiff2d(64, 30.0, 30.0), 0, 2e-3, 1e-3, 20),
     ("lap2d-30 p2 squarings", lambda: W.laplace2d(30), 2, 4e-3, 2e-3, 16),
+    # the largest Krylov dimension and p: exponential of order 137 (device-memory solve)
+    ("convdiff-64 p8 m128", lambda: W.convdiff2d(64, 30.0, 30.0), 8, 4e-4, 2e-4, 128),
 ]
 
 

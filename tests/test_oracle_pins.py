@@ -305,6 +305,19 @@ def test_phipm_vs_bruteforce(oracle_lib, seed, n, symm, p, t, tol):
     assert st["matvecs"] >= p * st["steps"] + st["steps"]
 
 
+def test_phipm_largest_sizes_vs_bruteforce(oracle_lib):
+    """Krylov dimension 128 and p = 8 (a small exponential of order 137), two
+    fixed substeps at tau ||A||_inf = 8, against the brute-force exponential of
+    the augmented matrix (eq. phide)."""
+    A = W.convdiff2d(32, 30.0, 30.0)
+    tau = 8.0 / abs(A).sum(axis=1).max()
+    b = np.random.default_rng(21).standard_normal((A.shape[0], 9))
+    u, st = oracle.phipm(2 * tau, A, b, tau_fixed=tau, m_init=128, m_max=128, adapt_m=0)
+    assert st["steps"] == 2 and st["m_last"] == 128 and st["matvecs"] == 2 * (128 + 8)
+    ref = brute_force(A, b, 2 * tau)
+    assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 def test_phipm_diagonal_closed_form(oracle_lib):
     n, p, t = 50, 3, 0.9
     d = -np.linspace(0.1, 40.0, n)
