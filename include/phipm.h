@@ -153,7 +153,9 @@ int phipm_last_status(void);
 int phipm_spmv(const phipm_csr* A, const double* x, double* y, phipm_stream_t stream);
 
 /* E = exp(H) for a dense row-major N x N float64 matrix on the device with the
- * solver's small-matrix exponential (degree-13 Pade, scaling and squaring).
+ * solver's small-matrix exponential (Sect. 3.1: scaling and squaring; here with
+ * a degree-18 Taylor polynomial of double-precision backward error instead of
+ * the degree-13 Pade approximant, so no linear solve).
  * N <= PHIPM_M_CAP + PHIPM_P_MAX + 1.  scratch: device, >= 8*N*N doubles. */
 int phipm_expm(int N, const double* H, double* E, double* scratch, phipm_stream_t stream);
 
