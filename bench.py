@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # the kernel sources and build script they were measured on; reported only while that hash
 # still matches (the summaries with their commands are under profiles/).
 MEASURED_TRAFFIC = {
-    "convdiff2d-512": ("4857e915e8268b63", 439132202848.0),
+    "convdiff2d-512": ("4118417031fc761f", 438875369118.0),
 }
 
 
@@ -37,7 +37,8 @@ def kernel_source_hash() -> str:
     import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_0907_4631_amd", "csrc", "*")))
+    files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_0907_4631_amd", "csrc", "*"))
+                   if os.path.isfile(f))
     files.append(os.path.join(ROOT, "paper_0907_4631_amd", "_build.py"))
     for f in files:
         with open(f, "rb") as fh:

@@ -2,10 +2,11 @@
 polynomial with scaling and squaring): the constant in the kernel source, the
 script that derives it, the published value, and the scalar backward error at
 the threshold computed in 80-digit arithmetic."""
-import importlib.util
 import math
 import os
 import re
+import runpy
+import types
 from decimal import Decimal, getcontext
 
 CSRC = os.path.join(os.path.dirname(__file__), "..", "paper_0907_4631_amd", "csrc")
@@ -13,11 +14,8 @@ U = 2.0 ** -53
 
 
 def _script():
-    spec = importlib.util.spec_from_file_location("taylor_theta",
-                                                  os.path.join(CSRC, "taylor_theta.py"))
-    mod = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(mod)
-    return mod
+    # run_path compiles without writing a bytecode cache beside the kernel sources
+    return types.SimpleNamespace(**runpy.run_path(os.path.join(CSRC, "taylor_theta.py")))
 
 
 def _kernel_theta() -> float:
