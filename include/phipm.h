@@ -152,6 +152,23 @@ int phipm_last_status(void);
  * Same validity rules as phipm(); asynchronous. */
 int phipm_spmv(const phipm_csr* A, const double* x, double* y, phipm_stream_t stream);
 
+/* Pointwise data of one exponential Rosenbrock-Euler step for the Allen-Cahn
+ * equation u_t = L u + u - u^3, the integrator that drives the solver the
+ * way Sect. 1 describes (one phi_1 evaluation per step, with the Jacobian
+ * J = L + diag(1 - 3 u^2) as the operator).  In order, on `stream`:
+ *   if du:    u += du                              (the previous step's increment)
+ *   if F:     F = L u + (u - u^3)                  (the right-hand side, b_1)
+ *   if J_val: J_val[diag_pos[i]] = lap_diag[i] + (1 - 3 u_i^2)   for i < n
+ * L: CSR of the linear part (device arrays, as for phipm()); u, du, F: device,
+ * n = L->n doubles (F must not alias u); diag_pos: device, n int32 positions of
+ * the diagonal in J's value array J_val (J shares L's pattern); lap_diag:
+ * device, the n diagonal values of L.  Any of du, F and J_val may be NULL;
+ * diag_pos and lap_diag are required with J_val.  Asynchronous.  Returns
+ * PHIPM_OK, PHIPM_EINVAL for a bad argument, PHIPM_EHIP. */
+int phipm_allen_cahn_update(const phipm_csr* L, double* u, const double* du,
+                            const int32_t* diag_pos, const double* lap_diag, double* J_val,
+                            double* F, phipm_stream_t stream);
+
 /* E = exp(H) for a dense row-major N x N float64 matrix on the device with the
  * solver's small-matrix exponential (Sect. 3.1: scaling and squaring; here with
  * a degree-18 Taylor polynomial of double-precision backward error instead of

@@ -100,7 +100,7 @@ EXPORTS = ["phipm_default_opts", "phipm_workspace_bytes", "phipm", "phipm_last_s
            "phipm_default_plan_opts", "phipm_plan_create", "phipm_plan_execute",
            "phipm_plan_stats", "phipm_plan_get_info", "phipm_plan_destroy", "phipm_batched",
            "phipm_batch_layout", "phipm_mlp_forward", "phipm_mlp_grad", "phipm_mlp_train",
-           "phipm_label_workspace_bytes", "phipm_label_steps"]
+           "phipm_label_workspace_bytes", "phipm_label_steps", "phipm_allen_cahn_update"]
 
 
 def lib():
@@ -162,6 +162,8 @@ def lib():
         L.phipm_label_steps.argtypes = [vp, C.c_int, vp, vp, vp, C.c_size_t,
                                         C.POINTER(LabelCosts), vp]
         L.phipm_label_steps.restype = C.c_int
+        L.phipm_allen_cahn_update.argtypes = [C.POINTER(CSR), vp, vp, vp, vp, vp, vp, vp]
+        L.phipm_allen_cahn_update.restype = C.c_int
         _lib = L
     return _lib
 
@@ -269,6 +271,17 @@ def spmv(A: DeviceCSR, x, y, stream=None):
                           _stream_ptr(stream))
     if rc != OK:
         raise PhipmError(rc, "phipm_spmv")
+
+
+def allen_cahn_update(L: DeviceCSR, u, du=None, diag_pos=None, lap_diag=None, J_val=None,
+                      F=None, stream=None):
+    """phipm_allen_cahn_update: u += du, F = L u + (u - u^3), and the Jacobian's
+    diagonal lap_diag + (1 - 3 u^2) into J_val at diag_pos (int32); None skips."""
+    p = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+    rc = lib().phipm_allen_cahn_update(C.byref(L.c()), p(u), p(du), p(diag_pos), p(lap_diag),
+                                       p(J_val), p(F), _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_allen_cahn_update")
 
 
 def expm(H, stream=None):

@@ -46,6 +46,38 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int n, const int* rp, const int*
   }
 }
 
+// u += du, elementwise.
+__global__ __launch_bounds__(256) void k_add_to(int n, double* u, const double* du) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256)
+    u[i] += du[i];
+}
+
+// Allen-Cahn step data, one row per thread: F = L u + (u - u^3) (the CSR
+// product as in k_spmv) and the Jacobian's diagonal lap_diag + (1 - 3 u^2)
+// at its positions in J's value array.  F or Jval may be null (skipped);
+// both nulls are excluded by the caller.
+__global__ __launch_bounds__(BLOCK) void k_allen_cahn(int n, const int* rp, const int* ci,
+                                                      const double* val, const double* u,
+                                                      const int* diag_pos,
+                                                      const double* lap_diag, double* Jval,
+                                                      double* F) {
+  __shared__ SpmvSmem<double> sm;
+  auto ld = [&](int c) -> double { return u[c]; };
+  for (long long r0 = (long long)blockIdx.x * BLOCK; r0 < n; r0 += (long long)gridDim.x * BLOCK) {
+    const int r1 = (int)std::min<long long>(r0 + BLOCK, n);
+    // F is the same for every thread of the launch, so the product's
+    // barriers are reached by all of them or by none
+    const double acc = F ? spmv_tile<double, double>(rp, ci, val, (int)r0, r1, sm, ld) : 0.0;
+    const int r = (int)r0 + threadIdx.x;
+    if (r < r1) {
+      const double ur = u[r];
+      if (F) F[r] = acc + (ur - ur * ur * ur);
+      if (Jval) Jval[diag_pos[r]] = lap_diag[r] + (1.0 - 3.0 * ur * ur);
+    }
+  }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_expm(int N, const double* H, double* E, double* S) {
   __shared__ double s_norm;
   __shared__ int s_sq;
@@ -325,6 +357,29 @@ int phipm_spmv(const phipm_csr* A, const double* x, double* y, phipm_stream_t st
   hipLaunchKernelGGL(k_spmv, dim3(grid), dim3(BLOCK), 0, stream, A->n, A->row_ptr, A->col_idx,
                      A->val, x, y);
   return hipGetLastError() == hipSuccess ? PHIPM_OK : PHIPM_EHIP;
+}
+
+int phipm_allen_cahn_update(const phipm_csr* L, double* u, const double* du,
+                            const int32_t* diag_pos, const double* lap_diag, double* J_val,
+                            double* F, phipm_stream_t stream_) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (!csr_ok(L) || !u || (J_val && (!diag_pos || !lap_diag))) return PHIPM_EINVAL;
+  const DeviceInfo* d = device_info();
+  if (!d) return PHIPM_EHIP;
+  const long long tiles = ((long long)L->n + BLOCK - 1) / BLOCK;
+  if (du) {
+    const long long blocks = ((long long)L->n + 255) / 256;
+    const int grid = (int)std::min<long long>(std::max<long long>(blocks, 1), (long long)d->cus * 16);
+    hipLaunchKernelGGL(k_add_to, dim3(grid), dim3(256), 0, stream, L->n, u, du);
+    if (hipGetLastError() != hipSuccess) return PHIPM_EHIP;
+  }
+  if (F || J_val) {
+    const int grid = (int)std::min<long long>(std::max<long long>(tiles, 1), (long long)d->cus * 8);
+    hipLaunchKernelGGL(k_allen_cahn, dim3(grid), dim3(BLOCK), 0, stream, L->n, L->row_ptr,
+                       L->col_idx, L->val, u, diag_pos, lap_diag, J_val, F);
+    if (hipGetLastError() != hipSuccess) return PHIPM_EHIP;
+  }
+  return PHIPM_OK;
 }
 
 int phipm_expm(int N, const double* H, double* E, double* scratch, phipm_stream_t stream_) {

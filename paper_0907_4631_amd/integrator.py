@@ -7,15 +7,15 @@ One step is one solver call (the paper's motivating use, its Sect. 1):
 
     u_{n+1} = u_n + h phi_1(h J_n) F(u_n),   F(u) = Lap u + u - u^3,
 
-i.e. phipm at t = h with b_0 = 0 and b_1 = F(u_n).  The product Lap u runs in
-the library's CSR kernel and the solve in its solver; the pointwise terms
-(u - u^3, the Jacobian's diagonal) are elementwise tensor updates.
+i.e. phipm at t = h with b_0 = 0 and b_1 = F(u_n).  The solve runs in the
+library's solver; F, the Jacobian's diagonal and the update u += h phi_1 F run
+in its phipm_allen_cahn_update kernels.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import FP64, DeviceCSR, Solver, spmv
+from . import FP64, DeviceCSR, Solver, allen_cahn_update
 
 
 class AllenCahnERE:
@@ -37,8 +37,9 @@ class AllenCahnERE:
         diag = np.nonzero(lap.indices == rows)[0]
         if diag.size != self.n:
             raise ValueError("the Laplacian must store its full diagonal")
-        self.diag = torch.as_tensor(diag, device=device)
-        self.lap_diag = self.L.val[self.diag].clone()
+        self.diag = torch.as_tensor(diag.astype(np.int32), device=device)
+        self.lap_diag = torch.as_tensor(np.asarray(lap.data[diag], dtype=np.float64),
+                                        device=device)
         self.u = torch.as_tensor(np.asarray(u0, dtype=np.float64), device=device).clone()
         self.solver = Solver(self.J, 1, tol=tol, precision=FP64, symm=1)
         self.hist = None
@@ -53,16 +54,14 @@ class AllenCahnERE:
 
     def rhs(self, out):
         """out <- F(u) = Lap u + u - u^3."""
-        spmv(self.L, self.u, out)
-        out.add_(self.u - self.u * self.u * self.u)
+        allen_cahn_update(self.L, self.u, F=out)
         return out
 
     def step(self, stats: bool = False):
-        u = self.u
-        self.J.val[self.diag] = self.lap_diag + (1.0 - 3.0 * u * u)
-        self.rhs(self.b[1])
+        allen_cahn_update(self.L, self.u, diag_pos=self.diag, lap_diag=self.lap_diag,
+                          J_val=self.J.val, F=self.b[1])
         st = self.solver(self.h, self.b, self.du, stats=stats)
-        u.add_(self.du)
+        allen_cahn_update(self.L, self.u, du=self.du)
         return st
 
     def run(self, steps: int, stats: bool = False):
