@@ -53,7 +53,22 @@ class TraceRec(C.Structure):
     _fields_ = [("t", C.c_double), ("tau", C.c_double), ("eps", C.c_double),
                 ("omega", C.c_double), ("beta", C.c_double), ("hnext", C.c_double),
                 ("anorm", C.c_double), ("tau_next", C.c_double), ("m", C.c_int32),
-                ("accepted", C.c_int32), ("step", C.c_int32), ("m_next", C.c_int32)]
+                ("accepted", C.c_int32), ("step", C.c_int32), ("m_next", C.c_int32),
+                ("branch", C.c_int32), ("have", C.c_int32)]
+
+
+class Attempt(C.Structure):
+    _fields_ = [("tau", C.c_double), ("eps", C.c_double), ("omega", C.c_double),
+                ("knorm", C.c_double), ("rem", C.c_double), ("nnz", C.c_double),
+                ("n", C.c_double), ("m_use", C.c_int32), ("m_req", C.c_int32),
+                ("m_cap", C.c_int32), ("lanczos", C.c_int32), ("p", C.c_int32),
+                ("adapt_m", C.c_int32), ("broke", C.c_int32), ("tau_fixed", C.c_int32)]
+
+
+class Decision(C.Structure):
+    _fields_ = [("tau_next", C.c_double), ("tau_new", C.c_double), ("m_new", C.c_double),
+                ("accept", C.c_int32), ("branch", C.c_int32), ("m_next", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class Alg4State(C.Structure):
@@ -105,6 +120,9 @@ def lib():
         L.oracle_alg4.argtypes = [C.POINTER(Alg4State), C.c_double, C.c_int, C.c_double,
                                   C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_decide.argtypes = [C.POINTER(Alg4State), C.POINTER(Attempt),
+                                    C.POINTER(Decision)]
+        L.oracle_decide.restype = None
         L.oracle_phipm.argtypes = [C.c_double, C.c_int, _ip, _ip, _dp, C.c_int, _dp,
                                    C.POINTER(Opts), _dp, C.POINTER(Stats),
                                    C.c_void_p, C.c_int, C.POINTER(C.c_int)]
@@ -216,6 +234,22 @@ def alg4(state: Alg4State, tau, m, eps, omega):
     lib().oracle_alg4(C.byref(state), tau, int(m), eps, omega, C.byref(tn), C.byref(mn),
                       C.byref(q), C.byref(k))
     return tn.value, mn.value, q.value, k.value
+
+
+def decide(state: Alg4State, **attempt):
+    """Algorithm 3's decision after one attempt; attempt fields as in
+    ``Attempt`` (m_req defaults to m_use, m_cap to 100, adapt_m to 1).
+    Returns a dict with accept, branch, tau_next, m_next, tau_new, m_new."""
+    a = Attempt()
+    a.m_cap, a.adapt_m = 100, 1
+    for k, v in attempt.items():
+        setattr(a, k, v)
+    if "m_req" not in attempt:
+        a.m_req = a.m_use
+    d = Decision()
+    lib().oracle_decide(C.byref(state), C.byref(a), C.byref(d))
+    return {"accept": bool(d.accept), "branch": d.branch, "tau_next": d.tau_next,
+            "m_next": d.m_next, "tau_new": d.tau_new, "m_new": d.m_new}
 
 
 def threads() -> int:

@@ -26,7 +26,10 @@
  *                        Adam's first step, brute-force omega scans.
  *   oracle_tau0, oracle_cost_*, oracle_alg4
  *                        pinned by properties (fixed points at omega=gamma,
- *                        recovery of a known order / decay rate).  The
+ *                        recovery of a known order / decay rate).
+ *   oracle_decide        pinned: hand-computed cases of acceptance at
+ *                        delta = 1.2, each clamp and both branches, and
+ *                        properties of every attempt of traced solves.  The
  *                        step-by-step trajectory of the controller has no
  *                        printed worked example: parity unpinned.
  */
@@ -66,6 +69,8 @@ typedef struct {
 typedef struct {
   double  t, tau, eps, omega, beta, hnext, anorm, tau_next;
   int32_t m, accepted, step, m_next;
+  int32_t branch;     /* 1 = tau changed, 2 = m changed, 0 = no decision */
+  int32_t have;       /* basis vectors built in this step so far */
 } oracle_trace_rec;
 
 enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_EMAXSTEPS = -5, ORACLE_ENONFINITE = -4 };
@@ -113,6 +118,27 @@ typedef struct {
  * proposals tau_new and m_new (eq. 2, eq. 3; m_new rounded up). */
 void   oracle_alg4(oracle_alg4_state* s, double tau, int m, double eps, double omega,
                    double* tau_new, double* m_new, double* q_used, double* k_used);
+
+/* One attempt as Algorithm 3 sees it when it decides. */
+typedef struct {
+  double  tau, eps, omega;  /* substep, estimate eq. errest, ratio eq. taunew */
+  double  knorm;            /* ||tau K||_1 of the attempt (M of eq. 8) */
+  double  rem;              /* t_end - t_k */
+  double  nnz, n;           /* N_A and n of eq. 4 */
+  int32_t m_use;            /* dimension the attempt used */
+  int32_t m_req;            /* dimension that was requested (> m_use after breakdown) */
+  int32_t m_cap, lanczos, p, adapt_m, broke, tau_fixed;
+} oracle_attempt;
+
+typedef struct {
+  double  tau_next, tau_new, m_new;  /* clamped tau, and the raw Algorithm 4 proposals */
+  int32_t accept, branch, m_next, pad_;
+} oracle_decision;
+
+/* Algorithm 3's decision after one attempt: acceptance (omega <= 1.2), the
+ * branch (1 = tau, 2 = m) by the cost comparison of eqs. 4-5, and the clamped
+ * tau / m of the next attempt.  Updates the Algorithm 4 memory in s. */
+void   oracle_decide(oracle_alg4_state* s, const oracle_attempt* a, oracle_decision* d);
 
 /* Full solver: u = phi_0(tA)b_0 + t phi_1(tA)b_1 + ... + t^p phi_p(tA) b_p.
  * b is n x (p+1) column-major.  trace may be NULL. */

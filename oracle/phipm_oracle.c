@@ -80,10 +80,22 @@ void oracle_spmv(int n, const int32_t* rp, const int32_t* ci, const double* val,
   }
 }
 
+/* Inner product summed over a fixed split of the rows into DOT_BLOCKS
+ * contiguous blocks, each summed in row order, then the block sums in block
+ * order: the result does not depend on the number of threads or on the order
+ * in which they finish. */
+enum { DOT_BLOCKS = 256 };
 static double dot(int n, const double* x, const double* y) {
+  double part[DOT_BLOCKS];
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < DOT_BLOCKS; ++k) {
+    const long lo = (long)n * k / DOT_BLOCKS, hi = (long)n * (k + 1) / DOT_BLOCKS;
+    double s = 0.0;
+    for (long i = lo; i < hi; ++i) s += x[i] * y[i];
+    part[k] = s;
+  }
   double s = 0.0;
-#pragma omp parallel for reduction(+ : s) schedule(static)
-  for (int i = 0; i < n; ++i) s += x[i] * y[i];
+  for (int k = 0; k < DOT_BLOCKS; ++k) s += part[k];
   return s;
 }
 
@@ -460,11 +472,82 @@ static double csr_norm_inf(const csr_t* A) {
   return best;
 }
 
+/* One decision of Algorithm 3 after an attempt: accept or reject (omega <=
+ * delta = 1.2), then which of tau and m to change for the next attempt (or the
+ * next step, on acceptance).  Algorithm 4 supplies the proposals tau_new
+ * (eq. 2) and m_new (eq. 3); the cheaper of C(tau_new, m) and C(tau, m_new)
+ * (eq. 4, eq. 5, with M of eq. 8 from ||tau K||_1 of this attempt) picks the
+ * branch.  Readings: ties choose the m-branch; the m-branch clamps m_new to
+ * [floor(3m/4), ceil(4m/3)], to at least 1 and to m_cap; tau is clamped to
+ * [tau/5, 2 tau] and to t_end - t; the tau-branch is taken when m is fixed,
+ * after a happy breakdown, or when rejecting and m cannot grow; a non-finite
+ * omega rejects and divides tau by 5; a fixed substep accepts everything. */
+void oracle_decide(oracle_alg4_state* s, const oracle_attempt* a, oracle_decision* d) {
+  const double delta = 1.2;
+  const double tau = a->tau;
+  memset(d, 0, sizeof(*d));
+  d->tau_next = tau;
+  d->m_next = a->m_req;
+  d->tau_new = tau;
+  d->m_new = a->m_use;
+  if (a->tau_fixed) {
+    d->accept = 1;
+    return;
+  }
+  if (!isfinite(a->omega)) {
+    d->accept = 0;
+    d->tau_next = tau / 5.0;
+    s->prev_rejected = 0;
+    return;
+  }
+  double tau_new, m_new;
+  oracle_alg4(s, tau, a->m_use, a->eps, a->omega, &tau_new, &m_new, NULL, NULL);
+  d->tau_new = tau_new;
+  d->m_new = m_new;
+  const double M = oracle_cost_M(a->knorm);
+  const double m_cost = m_new < 1.0 ? 1.0 : m_new;  /* Reading: dimension >= 1 */
+  const double c_tau =
+      oracle_cost_C(a->rem, tau_new, oracle_cost_C1(a->lanczos, a->m_use, a->p, a->nnz, a->n, M));
+  const double c_m =
+      oracle_cost_C(a->rem, tau, oracle_cost_C1(a->lanczos, m_cost, a->p, a->nnz, a->n, M));
+  const int accept = a->omega <= delta;
+  int m_cand = a->m_req;
+  if (a->adapt_m && !a->broke) {
+    double mm = m_new;
+    const double lo = floor(0.75 * a->m_use);
+    if (mm < lo) mm = lo;
+    if (mm < 1.0) mm = 1.0;
+    const double hi = ceil(4.0 * a->m_use / 3.0);
+    if (mm > hi) mm = hi;
+    if (mm > a->m_cap) mm = a->m_cap;
+    m_cand = (int)mm;
+  }
+  int branch;
+  if (c_tau < c_m || !a->adapt_m || a->broke || (!accept && m_cand <= a->m_use)) branch = 1;
+  else branch = 2;
+  if (branch == 1) {
+    double tn = tau_new;
+    if (tn < tau / 5.0) tn = tau / 5.0;
+    if (tn > 2.0 * tau) tn = 2.0 * tau;
+    if (tn > a->rem) tn = a->rem;
+    d->tau_next = tn;
+    d->m_next = a->m_use;
+  } else {
+    d->m_next = m_cand;
+  }
+  d->accept = accept;
+  d->branch = branch;
+  s->prev_branch = branch;
+  s->eps_old = a->eps;
+  s->tau_old = tau;
+  s->m_old = a->m_use;
+  s->prev_rejected = !accept;
+}
+
 /* Algorithm 3 with Algorithm 4. */
 int oracle_phipm(double t_end, int n, const int32_t* rp, const int32_t* ci, const double* val_in,
                  int p, const double* b_in, const oracle_opts* o, double* u,
                  oracle_stats* st, oracle_trace_rec* trace, int trace_cap, int* trace_len) {
-  const double delta = 1.2;
   oracle_stats stats;
   memset(&stats, 0, sizeof(stats));
   if (trace_len) *trace_len = 0;
@@ -577,63 +660,24 @@ int oracle_phipm(double t_end, int n, const int32_t* rp, const int32_t* ci, cons
         }
         const double omega = t_end * eps / (tau * o->tol);   /* eq. taunew */
 
-        int accept;
-        double tau_next = tau;
-        int m_next = m;
-        if (o->tau_fixed > 0.0) {
-          accept = 1;
-        } else if (!isfinite(omega)) {
-          /* Reading: a non-finite estimate rejects and shrinks tau by 5. */
-          accept = 0;
-          tau_next = tau / 5.0;
-          as.prev_rejected = 0;
-        } else {
-          double tau_new, m_new;
-          oracle_alg4(&as, tau, m_use, eps, omega, &tau_new, &m_new, NULL, NULL);
-          const double M = oracle_cost_M(knorm);
-          const double rem = t_end - t;
-          double m_cost = m_new < 1.0 ? 1.0 : m_new;  /* Reading: dimension >= 1 */
-          double c_tau = oracle_cost_C(rem, tau_new, oracle_cost_C1(lanczos, m_use, p, nnz, n, M));
-          double c_m = oracle_cost_C(rem, tau, oracle_cost_C1(lanczos, m_cost, p, nnz, n, M));
-          accept = omega <= delta;
-          int branch;
-          int m_cand = m;
-          if (o->adapt_m && !broke) {
-            double mm = m_new;
-            double lo = floor(0.75 * m_use);
-            if (mm < lo) mm = lo;
-            if (mm < 1.0) mm = 1.0;
-            double hi = ceil(4.0 * m_use / 3.0);
-            if (mm > hi) mm = hi;
-            if (mm > m_cap) mm = m_cap;
-            m_cand = (int)mm;
-          }
-          /* Reading: the m-branch is taken when it is not dearer; if m cannot
-           * move (fixed m, cap reached, breakdown) while rejecting, adapt tau. */
-          if (c_tau < c_m || !o->adapt_m || broke || (!accept && m_cand <= m_use)) branch = 1;
-          else branch = 2;
-          if (branch == 1) {
-            double tn = tau_new;
-            if (tn < tau / 5.0) tn = tau / 5.0;
-            if (tn > 2.0 * tau) tn = 2.0 * tau;
-            if (tn > rem) tn = rem;
-            tau_next = tn;
-            m_next = m_use;
-          } else {
-            m_next = m_cand;
-          }
-          as.prev_branch = branch;
-          as.eps_old = eps;
-          as.tau_old = tau;
-          as.m_old = m_use;
-          as.prev_rejected = !accept;
-        }
+        oracle_attempt at;
+        memset(&at, 0, sizeof(at));
+        at.tau = tau; at.eps = eps; at.omega = omega; at.knorm = knorm; at.rem = t_end - t;
+        at.nnz = (double)nnz; at.n = (double)n;
+        at.m_use = m_use; at.m_req = m; at.m_cap = m_cap; at.lanczos = lanczos; at.p = p;
+        at.adapt_m = o->adapt_m; at.broke = broke; at.tau_fixed = o->tau_fixed > 0.0;
+        oracle_decision dc;
+        oracle_decide(&as, &at, &dc);
+        const int accept = dc.accept;
+        const double tau_next = dc.tau_next;
+        const int m_next = dc.m_next;
 
         if (trace && trace_len && *trace_len < trace_cap) {
           oracle_trace_rec* r = &trace[(*trace_len)++];
           r->t = t; r->tau = tau; r->eps = eps; r->omega = omega; r->beta = beta;
           r->hnext = hnext; r->anorm = anorm; r->tau_next = tau_next;
           r->m = m_use; r->accepted = accept; r->step = (int)stats.steps; r->m_next = m_next;
+          r->branch = dc.branch; r->have = have;
         }
 
         if (accept) {
