@@ -2,9 +2,14 @@
 
 One step = one full adaptive solve u = sum_k t^k phi_k(tA) b_k to t_end on a
 synthetic workload whose inputs are already resident in HBM.  Prints one JSON
-line with solves/s, the roofline position of the solver kernel (algorithmic
-bytes per solve / measured solve time against the 8 TB/s HBM peak) and the CPU
-oracle timed on a bounded sample of the same solve.
+line.  The default run measures the 512^2 convection-diffusion solve (Arnoldi,
+FP64, tol 1e-8): solves/s, the roofline position of the solver kernel (the
+reference byte model of a plain CGS2 Krylov step per solve / the measured
+solve time, against the 8 TB/s HBM peak), the relative error against the CPU
+oracle, the oracle's own time on the host cores, and, under "headline", the
+200-call sequence of the 1024^2 reaction-diffusion operator at tol 1e-6 with
+the learned (tau, m) proposer and the FP32 basis against the plain FP64
+method.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -13,6 +18,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -22,14 +28,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 << 20
 
 # HBM bytes per solver launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE
-# (scaled against a plain device copy), keyed by workload and by the hash of
-# the kernel sources and build script they were measured on; reported only while that hash
-# still matches (the summaries with their commands are under profiles/).
-MEASURED_TRAFFIC = {
-    "convdiff2d-512": ("fd823326c946c3f1", 438913824394.0),
-}
+# (scaled against a plain device copy), keyed by workload: (hash of the kernel
+# sources and build script they were measured on, bytes, summary file).  A
+# value is reported only while that hash still matches.
+MEASURED_TRAFFIC = {}
 
 
 def kernel_source_hash() -> str:
@@ -45,83 +50,302 @@ def kernel_source_hash() -> str:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
+
 WORKLOADS = {
-    # name: (builder, description, basis precision)
+    # name: (builder, description, basis precision, CSR value type)
     "convdiff2d-512": ("config2", "2D upwind convection-diffusion 512x512 (n=262144, D=1, "
-                       "v=(50,50)), p=2, t=1e-2, tol=1e-8, Arnoldi, FP64", "fp64"),
+                       "v=(50,50)), p=2, t=1e-2, tol=1e-8, Arnoldi, FP64", "fp64", "f64"),
     "laplace3d-128": ("config3", "3D 7-point Laplacian 128^3 (n=2097152), p=3, t=1e-4, "
-                      "tol=1e-6, Lanczos", "fp64"),
+                      "tol=1e-6, Lanczos", "fp64", "f32"),
     "laplace2d-30": ("config1", "2D 5-point Laplacian 30x30 (n=900), p=1, t=1e-3, tol=1e-7, "
-                     "Lanczos, FP64", "fp64"),
+                     "Lanczos, FP64", "fp64", "f64"),
+    "reaction2d-1024": ("config5_call0", "2D diffusion-reaction Jacobian 1024x1024 (Laplacian + "
+                        "diag(1 - 3 u^2), n=1048576), p=2, t=1e-3, tol=1e-6, one call, Lanczos",
+                        "fp64", "f64"),
     "reaction2d-1024-calls": ("config5", "2D diffusion-reaction Jacobian 1024x1024 "
                               "(Laplacian + diag(1 - 3 u^2), n=1048576), p=2, t=1e-3, tol=1e-6, "
-                              "successive calls with new b; learned (tau, m) proposer vs plain "
-                              "step control (cold and warm start)", "fp64"),
+                              "successive calls with new b; learned (tau, m) proposer + FP32 "
+                              "basis vs the plain FP64 method (cold and warm start)", "fp64",
+                              "f64"),
     "allencahn-1024-ere": ("config5", "Allen-Cahn u_t = Lap u + u - u^3 on the 1024x1024 grid "
-                           "(n=1048576) from the config-5 field, exponential Rosenbrock-Euler "
-                           "steps h=1e-3, one phipm call per step (p=1, tol=1e-6, Lanczos); "
-                           "learned (tau, m) proposer vs plain step control (cold and warm)",
-                           "fp64"),
+                           "(n=1048576) from the reaction-diffusion field, exponential "
+                           "Rosenbrock-Euler steps h=1e-3, one phipm call per step (p=1, "
+                           "tol=1e-6, Lanczos); learned (tau, m) proposer vs plain step control "
+                           "(cold and warm)", "fp64", "f64"),
     "heston-100x51": ("heston_problem", "finite-difference Heston operator on the 100x51 grid "
-                      "of the paper's Sect. 5.1 (n=5100), p=1, t=T=1, tol=1e-6, Arnoldi, FP64",
-                      "fp64"),
+                      "of the paper's Sect. 4.1 (n=5100), p=1, t=T=1, tol=1e-6, Arnoldi, FP64",
+                      "fp64", "f64"),
     "convdiff2d-batch256": ("config4", "256 independent 2D upwind convection-diffusion solves "
                             "(N_i in 32..256, Peclet in 0..100, p_i in 0..3, t_i in 1e-4..1e-1, "
                             "tol=1e-7) in one persistent autotuned launch replayed from a hipGraph",
-                            "fp64"),
+                            "fp64", "f64"),
 }
+
+METRIC = "phipm solves/s (adaptive Krylov phi-function solve to t_end) and HBM GB/s"
 
 
 def build_problem(name):
     import workloads as W
-    return getattr(W, WORKLOADS[name][0])()
+    b = WORKLOADS[name][0]
+    if b == "config5_call0":
+        A = W.config5_matrix()
+        pb = W.Problem("reaction2d-1024-call0", A, W.config5_b(0, A.shape[0]), 1e-3, 1e-6, True)
+        return pb
+    return getattr(W, b)()
 
 
-def cpu_baseline(pb, gpu_attempts, budget_s=20.0):
-    """The oracle on the host cores, timed on the first attempts of the same
-    solve and scaled to the attempts the GPU solve needed."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_reference(pb, runs=3, budget_s=45.0, single_budget_s=10.0):
+    """The oracle on the host cores: the whole solve timed `runs` times
+    (median; fewer when one run is long), its solution (for the error of the
+    GPU result), and a single-thread figure from the first attempts of the
+    same solve, scaled by attempt count."""
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    _, st = oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol, max_attempts=2, allow_limit=True)
-    t_probe = time.perf_counter() - t0
-    per = t_probe / max(1, st["steps"] + st["rejected"])
-    k = int(max(2, min(gpu_attempts, budget_s / max(per, 1e-9))))
-    t0 = time.perf_counter()
-    _, st = oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol, max_attempts=k, allow_limit=True)
-    dt = time.perf_counter() - t0
-    done = max(1, st["steps"] + st["rejected"])
-    per_solve = dt * gpu_attempts / done
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"first {done} of the {gpu_attempts} attempts of one solve "
-                      f"({dt:.1f} s), scaled by attempt count"}
-
-
-def cpu_baseline_batch(probs, gpu_stats, budget_s=20.0, seed=7):
-    """The oracle on the host cores, timed on a seeded random sample of the
-    batch's instances (about budget_s of CPU work) and scaled to the whole
-    batch by rows x products (the GPU run's product counts)."""
-    import oracle
-    oracle.build(force=False)
-    order = np.random.default_rng(seed).permutation(len(probs))
-    spent, work_done, done = 0.0, 0.0, 0
-    for i in order:
-        pb = probs[i]
-        w = pb.n * max(1, gpu_stats[i]["matvecs"])
+    threads = oracle.threads()
+    times, u, st = [], None, None
+    for _ in range(runs):
         t0 = time.perf_counter()
-        oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol)
-        spent += time.perf_counter() - t0
-        work_done += w
-        done += 1
-        if spent > budget_s:
+        u, st = oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol)
+        times.append(time.perf_counter() - t0)
+        if sum(times) > budget_s:
             break
-    total = sum(pb.n * max(1, s["matvecs"]) for pb, s in zip(probs, gpu_stats))
-    per_batch = spent * total / work_done
-    return {"value": len(probs) / per_batch, "unit": "solves/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{done} randomly chosen of the {len(probs)} instances ({spent:.1f} s), "
-                      f"scaled to the batch by rows x products"}
+    per_solve = float(np.median(times))
+    attempts = st["steps"] + st["rejected"]
+    # one thread, bounded sample: the first k attempts
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, s1 = oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol, max_attempts=1, allow_limit=True)
+        t1 = time.perf_counter() - t0
+        k = int(max(1, min(attempts, single_budget_s / max(t1, 1e-9))))
+        if k > 1:
+            t0 = time.perf_counter()
+            _, s1 = oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol, max_attempts=k, allow_limit=True)
+            t1 = time.perf_counter() - t0
+        done = max(1, s1["steps"] + s1["rejected"])
+        single = t1 * attempts / done
+    finally:
+        oracle.set_threads(threads)
+    base = {"value": 1.0 / per_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole solve, {len(times)} run(s), median {per_solve:.2f} s "
+                      f"({attempts} attempts); single thread: the first {done} attempts "
+                      f"({t1:.1f} s) scaled by attempt count",
+            "single_thread_value": 1.0 / single, "cpu_model": cpu_model(),
+            "build": "gcc " + " ".join(oracle.CFLAGS[:3]),
+            "oracle_stats": {k: st[k] for k in ("steps", "rejected", "matvecs", "expms")}}
+    return u, base
+
+
+def rel_err(u, ref):
+    return float(np.linalg.norm(u - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def time_solves(solver, t, b, u, steps, warmup):
+    import torch
+    st = None
+    for _ in range(max(1, warmup)):
+        st = solver(t, b, u, stats=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        solver(t, b, u, stats=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, st
+
+
+def run_single(args, with_headline):
+    import torch
+    import paper_0907_4631_amd as pk
+    pb = build_problem(args.workload)
+    if args.tol > 0.0:
+        pb.tol = args.tol
+    precision = pk.FP32_BASIS if args.precision == "fp32" else pk.FP64
+    vdt = np.float32 if args.values == "f32" else np.float64
+    if vdt == np.float32 and not np.array_equal(pb.A.data.astype(np.float32).astype(np.float64),
+                                                pb.A.data):
+        vdt = np.float64   # the operator is not exact in float32: keep it as it is
+    A = pk.DeviceCSR(pb.A, device="cuda", dtype=vdt)
+    b = torch.as_tensor(np.ascontiguousarray(pb.b.T), device="cuda")
+    u = torch.empty(pb.n, dtype=torch.float64, device="cuda")
+    kw = {}
+    if args.fixed_m > 0:
+        kw = dict(adapt_m=0, m_init=args.fixed_m, m_max=args.fixed_m)
+    solver = pk.Solver(A, pb.p, tol=pb.tol, precision=precision, workgroups=args.workgroups,
+                       validate=1, **kw)
+    ms, st = time_solves(solver, pb.t, b, u, args.steps, args.warmup)
+    status = pk.lib().phipm_last_status()
+    if status != 0:
+        raise pk.PhipmError(status, "timed solve")
+    u_gpu = u.cpu().numpy()
+
+    sec = ms / 1e3
+    achieved = st["bytes_ref"] / sec / 1e9
+    traffic, traffic_src = None, None
+    default_run = (args.fixed_m == 0 and args.tol == 0.0 and args.workgroups == 0 and
+                   args.precision == WORKLOADS[args.workload][2])
+    if default_run and args.workload in MEASURED_TRAFFIC:
+        sha, nbytes, src = MEASURED_TRAFFIC[args.workload]
+        if sha == kernel_source_hash():
+            traffic, traffic_src = nbytes, src
+    s = 4.0 if precision == pk.FP32_BASIS else 8.0
+    sv = 4.0 if vdt == np.float32 else 8.0
+    work_set = ((sv + 4.0) * pb.A.nnz + 4.0 * (pb.n + 1) +
+                s * pb.n * (st["m_last"] + 3) + 8.0 * pb.n * (pb.p + 2))
+    line = {
+        "metric": METRIC, "value": 1.0 / sec, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == pk.FP64 else "f32-basis/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOADS[args.workload][1] +
+                        (f" (tolerance overridden: tol={pb.tol:g})" if args.tol > 0.0 else ""),
+            "n": pb.n, "nnz": int(pb.A.nnz), "p": pb.p, "t": pb.t, "tol": pb.tol,
+            "workgroups": st["workgroups"], "lanczos": st["lanczos"],
+            "csr_values": "f32" if vdt == np.float32 else "f64",
+            "method": f"phip (m fixed at {args.fixed_m})" if args.fixed_m > 0 else "phipm",
+            "solve_stats": {k: st[k] for k in ("steps", "rejected", "matvecs", "expms",
+                                                "m_last", "fp64_steps",
+                                                "fp32_error_estimate")},
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_solve (persistent solver: CSR products, Krylov steps, small "
+                      "exponential, control)",
+            "algorithmic_bytes_per_launch": st["bytes_ref"],
+            "bytes_model": "reference plain-CGS2 model: per basis vector j+1 the CSR product "
+                           "(s+4) nnz + 4(n+1) + 2 s n plus (4(j+1)+8) s n (Arnoldi) or 16 s n "
+                           "(Lanczos); per step p products + 3p vectors (w-recurrence) and "
+                           "(p+m+2) vectors (update)",
+            "streamed_bytes_per_launch": st["bytes"],
+            "frac_streamed": st["bytes"] / sec / 1e9 / HBM_PEAK_GBS,
+            "working_set_bytes": work_set,
+            "fits_infinity_cache": bool(work_set <= INFINITY_CACHE_BYTES),
+        },
+    }
+    if traffic_src:
+        line["roofline"]["traffic_source"] = traffic_src
+    if not args.no_cpu:
+        ref, base = oracle_reference(pb)
+        line["err_vs_oracle"] = rel_err(u_gpu, ref)
+        line["cpu_baseline"] = base
+    if with_headline and not args.no_headline:
+        line["headline"] = run_calls_block(args, calls=args.calls, warmup=1,
+                                           oracle_calls=not args.no_cpu)
+    print(json.dumps(line), flush=True)
+
+
+CALL_VARIANTS = [
+    # name, basis, proposer, warm start
+    ("plain-fp64-cold", "fp64", False, False),
+    ("plain-fp64-warm", "fp64", False, True),
+    ("learned-fp64", "fp64", True, False),
+    ("plain-fp32", "fp32", False, False),
+    ("learned-fp32", "fp32", True, False),
+]
+
+
+def run_calls_block(args, calls, warmup, oracle_calls=True):
+    """Successive calls on the 1024^2 reaction-diffusion operator with new
+    right-hand sides (call c draws b from seed 5000 + c), t = 1e-3, tol = 1e-6,
+    in every variant; calls/s from HIP events around all calls, the step
+    counters from an untimed repeat, and the relative error against the oracle
+    on evenly spaced calls."""
+    import torch
+    import paper_0907_4631_amd as pk
+    from paper_0907_4631_amd import proposer as PR
+    import workloads as W
+    A = W.config5_matrix()
+    n = A.shape[0]
+    t, tol = 1e-3, 1e-6
+    Ad = pk.DeviceCSR(A)
+    bs = [torch.as_tensor(np.ascontiguousarray(W.config5_b(c, n).T), device="cuda")
+          for c in range(calls)]
+    weights = PR.load()
+    check = sorted(set(np.linspace(0, calls - 1, min(calls, 6)).astype(int).tolist()))
+    res, outs = {}, {}
+    for name, basis, learned, warm in CALL_VARIANTS:
+        s = pk.Solver(Ad, 2, tol=tol, precision=pk.FP32_BASIS if basis == "fp32" else pk.FP64)
+        hist = torch.zeros(4, dtype=torch.float64, device="cuda")
+        if warm:
+            s.opts.history = hist.data_ptr()
+        if learned:
+            s.opts.proposer = weights.data_ptr()
+        u = torch.empty(n, dtype=torch.float64, device="cuda")
+        for w in range(max(1, warmup)):
+            s(t, bs[w % calls], u, stats=False)
+        hist.zero_()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for c in range(calls):
+            s(t, bs[c], u, stats=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / calls
+        if pk.lib().phipm_last_status() != 0:
+            raise pk.PhipmError(pk.lib().phipm_last_status(), name)
+        hist.zero_()
+        tot = {"steps": 0, "rejected": 0, "matvecs": 0, "fp64_steps": 0}
+        outs[name] = {}
+        for c in range(calls):   # counters (and the checked solutions) from an untimed repeat
+            st = s(t, bs[c], u)
+            for k in tot:
+                tot[k] += st[k]
+            if c in check:
+                outs[name][c] = u.cpu().numpy()
+        res[name] = {"ms_per_call": ms, "calls_per_s": 1e3 / ms, **tot}
+    block = {"workload": WORKLOADS["reaction2d-1024-calls"][1], "calls": calls,
+             "timed_variant": "learned-fp32", "baseline_variant": "plain-fp64-cold",
+             "variants": res}
+    block["speedup_vs_plain_fp64"] = (res["learned-fp32"]["calls_per_s"] /
+                                      res["plain-fp64-cold"]["calls_per_s"])
+    if oracle_calls:
+        import oracle
+        oracle.build(force=False)
+        errs = {name: [] for name in res}
+        for c in check:
+            ref, _ = oracle.phipm(t, A, W.config5_b(c, n), tol=tol)
+            for name in res:
+                errs[name].append(rel_err(outs[name][c], ref))
+        for name in res:
+            res[name]["max_err_vs_oracle"] = max(errs[name])
+            res[name]["mean_err_vs_oracle"] = float(np.mean(errs[name]))
+        block["err_checked_calls"] = check
+    return block
+
+
+def run_calls(args):
+    block = run_calls_block(args, calls=args.steps, warmup=args.warmup,
+                            oracle_calls=not args.no_cpu)
+    v = block["variants"]["learned-fp32"]
+    line = {
+        "metric": METRIC, "value": v["calls_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": v["ms_per_call"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-basis/f64", "data": "synthetic",
+        "config": {"workload": block["workload"], "n": 1048576, "calls": args.steps,
+                   "variants": block["variants"],
+                   "speedup_vs_plain_fp64": block["speedup_vs_plain_fp64"]},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def run_integrator(args):
@@ -140,7 +364,7 @@ def run_integrator(args):
     for name in ("learned", "plain-cold", "plain-warm"):
         kw = {"proposer": PR.load()} if name == "learned" else {"warm": name == "plain-warm"}
         ig = integrator.AllenCahnERE(lap, u0, h, tol=tol, **kw)
-        sts = ig.run(max(1, args.warmup), stats=True)        # untimed, then restart from u0
+        ig.run(max(1, args.warmup), stats=True)        # untimed, then restart from u0
         ig.u.copy_(torch.as_tensor(u0, device="cuda"))
         if ig.hist is not None:
             ig.hist.zero_()
@@ -169,8 +393,7 @@ def run_integrator(args):
                                                     max(1.0, np.linalg.norm(ref)))
     ms = res["learned"]["ms_per_step"]
     line = {
-        "metric": "phipm solves/s (adaptive Krylov phi-function solve to t_end) and HBM GB/s",
-        "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": steps,
+        "metric": METRIC, "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOADS["allencahn-1024-ere"][1], "n": N * N, "h": h,
@@ -179,78 +402,30 @@ def run_integrator(args):
     print(json.dumps(line), flush=True)
 
 
-def run_calls(args):
-    """Successive calls on one operator with new right-hand sides: the
-    learned proposer (the timed variant) beside the plain step control cold
-    and warm-started, and the FP32 basis."""
-    import torch
-    import paper_0907_4631_amd as pk
-    from paper_0907_4631_amd import proposer as PR
-    import workloads as W
-    A = W.config5_matrix()
-    n = A.shape[0]
-    t, tol, calls = 1e-3, 1e-6, args.steps
-    Ad = pk.DeviceCSR(A)
-    bs = [torch.as_tensor(np.ascontiguousarray(W.config5_b(c, n).T), device="cuda")
-          for c in range(calls)]
-    weights = PR.load()
-    variants = [("learned", pk.FP64, True, False), ("plain-cold", pk.FP64, False, False),
-                ("plain-warm", pk.FP64, False, True), ("learned-fp32-basis", pk.FP32_BASIS, True,
-                                                        False)]
-    res, outs = {}, {}
-    for name, prec, learned, warm in variants:
-        s = pk.Solver(Ad, 2, tol=tol, precision=prec)
-        hist = torch.zeros(4, dtype=torch.float64, device="cuda")
-        if warm:
-            s.opts.history = hist.data_ptr()
-        if learned:
-            s.opts.proposer = weights.data_ptr()
-        us = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(calls)]
-        for w in range(max(1, args.warmup)):
-            s(t, bs[w % calls], us[0], stats=False)
-        hist.zero_()
-        torch.cuda.synchronize()
-        tot = {"steps": 0, "rejected": 0, "matvecs": 0, "fp64_fallbacks": 0}
-        stream = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for c in range(calls):
-            s(t, bs[c], us[c], stats=False)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / calls
-        if pk.lib().phipm_last_status() != 0:
-            raise pk.PhipmError(pk.lib().phipm_last_status(), name)
-        for c in range(calls):   # statistics from an untimed repeat of every call
-            st = s(t, bs[c], us[c])
-            for k in ("steps", "rejected", "matvecs"):
-                tot[k] += st[k]
-            tot["fp64_fallbacks"] += st["fp64_fallback"]
-        outs[name] = [u.cpu().numpy() for u in us]
-        res[name] = {"ms_per_call": ms, "calls_per_s": 1e3 / ms, **tot}
-    ref = outs["plain-cold"]
-    for name in res:
-        res[name]["max_diff_vs_plain_cold"] = max(
-            float(np.linalg.norm(a - b) / max(1.0, np.linalg.norm(b)))
-            for a, b in zip(outs[name], ref))
-    ms = res["learned"]["ms_per_call"]
-    line = {
-        "metric": "phipm solves/s (adaptive Krylov phi-function solve to t_end) and HBM GB/s",
-        "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": calls,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS["reaction2d-1024-calls"][1], "n": n, "nnz": int(A.nnz),
-                   "calls": calls, "variants": res},
-    }
-    if not args.no_cpu:
-        class _P:
-            pass
-        pb = _P()
-        pb.A, pb.b, pb.t, pb.tol = A, W.config5_b(0, n), t, tol
-        line["cpu_baseline"] = cpu_baseline(pb, max(1, res["plain-cold"]["steps"] +
-                                                     res["plain-cold"]["rejected"]) // calls)
-        line["cpu_baseline"]["sample"] += " (plain step control, one call)"
-    print(json.dumps(line), flush=True)
+def cpu_baseline_batch(probs, gpu_stats, budget_s=20.0, seed=7):
+    """The oracle on the host cores, timed on a seeded random sample of the
+    batch's instances (about budget_s of CPU work) and scaled to the whole
+    batch by rows x products (the GPU run's product counts)."""
+    import oracle
+    oracle.build(force=False)
+    order = np.random.default_rng(seed).permutation(len(probs))
+    spent, work_done, done = 0.0, 0.0, 0
+    for i in order:
+        pb = probs[i]
+        w = pb.n * max(1, gpu_stats[i]["matvecs"])
+        t0 = time.perf_counter()
+        oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol)
+        spent += time.perf_counter() - t0
+        work_done += w
+        done += 1
+        if spent > budget_s:
+            break
+    total = sum(pb.n * max(1, s["matvecs"]) for pb, s in zip(probs, gpu_stats))
+    per_batch = spent * total / work_done
+    return {"value": len(probs) / per_batch, "unit": "solves/s", "cores": oracle.threads(),
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{done} randomly chosen of the {len(probs)} instances ({spent:.1f} s), "
+                      f"scaled to the batch by rows x products"}
 
 
 def run_batch(args):
@@ -284,12 +459,11 @@ def run_batch(args):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
     plan.stats()   # raises on a device-side error of the timed runs
+    nref = sum(s["bytes_ref"] for s in st)
     nbytes = sum(s["bytes"] for s in st)
-    achieved = nbytes / (ms / 1e3) / 1e9
+    achieved = nref / (ms / 1e3) / 1e9
     line = {
-        "metric": "phipm solves/s (adaptive Krylov phi-function solve to t_end) and HBM GB/s",
-        "value": len(probs) / (ms / 1e3),
-        "unit": "solves/s",
+        "metric": METRIC, "value": len(probs) / (ms / 1e3), "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if precision == pk.FP64 else "f32-basis/f64",
@@ -305,13 +479,15 @@ def run_batch(args):
             "solve_stats": {"steps": sum(s["steps"] for s in st),
                             "rejected": sum(s["rejected"] for s in st),
                             "matvecs": sum(s["matvecs"] for s in st),
-                            "fp64_fallbacks": sum(s["fp64_fallback"] for s in st)},
+                            "fp64_steps": sum(s["fp64_steps"] for s in st)},
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "k_batch (persistent batched solver)",
-            "algorithmic_bytes_per_launch": nbytes,
+            "algorithmic_bytes_per_launch": nref,
+            "streamed_bytes_per_launch": nbytes,
+            "frac_streamed": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         },
     }
     if not args.no_cpu:
@@ -326,10 +502,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="convdiff2d-512", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="default workload: skip the 200-call learned + FP32 comparison")
+    ap.add_argument("--calls", type=int, default=200,
+                    help="calls of the headline comparison (default 200)")
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
                     help="basis precision (default: the workload's)")
+    ap.add_argument("--values", choices=["f64", "f32"], default=None,
+                    help="CSR value type on the device (default: the workload's; float32 only "
+                         "when every value is exact in float32)")
     ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the autotuner")
     ap.add_argument("--fixed-m", type=int, default=0, metavar="M",
                     help="single solves: the paper's phip (Krylov dimension fixed at M, only tau "
@@ -347,7 +530,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_0907_4631_amd as pk
 
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 8
@@ -362,94 +544,18 @@ def main():
 
     if args.precision is None:
         args.precision = WORKLOADS[args.workload][2]
+    if args.values is None:
+        args.values = WORKLOADS[args.workload][3]
     if args.workload == "convdiff2d-batch256":
         run_batch(args)
-        return
-    if args.workload == "reaction2d-1024-calls":
+    elif args.workload == "reaction2d-1024-calls":
         run_calls(args)
-        return
-    if args.workload == "allencahn-1024-ere":
+    elif args.workload == "allencahn-1024-ere":
         run_integrator(args)
-        return
-    pb = build_problem(args.workload)
-    if args.tol > 0.0:
-        pb.tol = args.tol
-    A = pk.DeviceCSR(pb.A, device="cuda")
-    b = torch.as_tensor(np.ascontiguousarray(pb.b.T), device="cuda")
-    u = torch.empty(pb.n, dtype=torch.float64, device="cuda")
-    precision = pk.FP32_BASIS if args.precision == "fp32" else pk.FP64
-    kw = {}
-    if args.fixed_m > 0:
-        kw = dict(adapt_m=0, m_init=args.fixed_m, m_max=args.fixed_m)
-    solver = pk.Solver(A, pb.p, tol=pb.tol, precision=precision, workgroups=args.workgroups,
-                       validate=1, **kw)
-    st = None
-    for _ in range(max(1, args.warmup)):
-        st = solver(pb.t, b, u, stats=True)
+    else:
+        run_single(args, with_headline=args.workload == "convdiff2d-512")
+    # release the library's device resources while the runtime is up
     torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        solver(pb.t, b, u, stats=False)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    status = pk.lib().phipm_last_status()
-    if status != 0:
-        raise pk.PhipmError(status, "timed solve")
-
-    per_solve_s = ms / 1e3
-    achieved = st["bytes"] / per_solve_s / 1e9
-    traffic = None
-    default_run = (args.fixed_m == 0 and args.tol == 0.0 and args.workgroups == 0 and
-                   args.precision == WORKLOADS[args.workload][2])
-    if default_run and args.workload in MEASURED_TRAFFIC:
-        # the counters were taken on the workload's own configuration only
-        sha, nbytes = MEASURED_TRAFFIC[args.workload]
-        if sha == kernel_source_hash():
-            traffic = nbytes
-    attempts = st["steps"] + st["rejected"]
-    line = {
-        "metric": "phipm solves/s (adaptive Krylov phi-function solve to t_end) and HBM GB/s",
-        "value": 1.0 / per_solve_s,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if precision == pk.FP64 else "f32-basis/f64",
-        "data": "synthetic",
-        "config": {
-            "workload": WORKLOADS[args.workload][1] +
-                        (f" (tolerance overridden: tol={pb.tol:g})" if args.tol > 0.0 else ""),
-            "n": pb.n, "nnz": int(pb.A.nnz), "p": pb.p, "t": pb.t, "tol": pb.tol,
-            "workgroups": st["workgroups"], "lanczos": st["lanczos"],
-            "method": f"phip (m fixed at {args.fixed_m})" if args.fixed_m > 0 else "phipm",
-            "solve_stats": {k: st[k] for k in ("steps", "rejected", "matvecs", "expms",
-                                                "m_last", "fp64_fallback",
-                                                "fp32_error_estimate")},
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "k_solve (persistent solver)",
-            "algorithmic_bytes_per_launch": st["bytes"],
-        },
-    }
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(pb, attempts)
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

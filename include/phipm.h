@@ -50,13 +50,17 @@ enum { PHIPM_FP64 = 0, PHIPM_FP32_BASIS = 1 };
 
 /* Square n x n CSR matrix, 0-based, columns strictly increasing within each
  * row.  All three arrays are device pointers owned by the caller; val holds
- * float64 entries.  Read-only for the library. */
+ * float64 (val_dtype = PHIPM_F64) or float32 (PHIPM_F32) entries, and the
+ * matrix is exactly those values: the solver reads them in that type and
+ * accumulates every product in float64.  Read-only for the library. */
 typedef struct {
   int32_t n;
   int32_t nnz;
   const int32_t* row_ptr; /* device, n+1 entries, row_ptr[0] = 0, row_ptr[n] = nnz */
   const int32_t* col_idx; /* device, nnz entries */
-  const double* val;      /* device, nnz entries */
+  const void* val;        /* device, nnz entries of type val_dtype */
+  int32_t val_dtype;      /* PHIPM_F64 (0) or PHIPM_F32 (1) */
+  int32_t pad_;
 } phipm_csr;
 
 /* Options.  Defaults from phipm_default_opts(). */
@@ -65,11 +69,13 @@ typedef struct {
   int32_t symm;          /* -1: detect exact symmetry (Sect. 3.5), 0: Arnoldi, 1: Lanczos */
   int32_t m_init;        /* initial Krylov dimension; default 10 (Algorithm 3) */
   int32_t m_max;         /* largest Krylov dimension; default 100, at most PHIPM_M_CAP */
-  int32_t precision;     /* PHIPM_FP64, or PHIPM_FP32_BASIS: Krylov basis and CSR values
-                            stored in FP32 (products and sums accumulated in FP64; W, u,
-                            the small exponential and the control in FP64), with a
-                            per-solve fallback to FP64 when its rounding estimate would
-                            not fit the tolerance (see phipm_stats.fp64_fallback) */
+  int32_t precision;     /* PHIPM_FP64, or PHIPM_FP32_BASIS: Krylov basis stored in FP32
+                            (products and sums accumulated in FP64; the CSR values in
+                            their own type; W, u, the small exponential and the control
+                            in FP64).  Each step picks its basis type: FP32 while the
+                            summed FP32 rounding estimates eps32 ||beta y|| of the
+                            steps fit tol max(1, ||u||), FP64 for a step that would not
+                            fit (see phipm_stats.fp64_steps and fp32_flags) */
   int32_t adapt_m;       /* 1: adapt m (phipm); 0: keep m fixed (the phip variant) */
   int32_t corrector;     /* 1: eq. phipapprox2 (default); 0: eq. phipapprox */
   double tau_fixed;      /* > 0: fixed substep, every attempt accepted (diagnostics) */
@@ -88,8 +94,19 @@ typedef struct {
   void* trace;           /* device, trace_cap phipm_trace_step records, or NULL: one record
                             per accepted step (training data of the proposer) */
   int32_t trace_cap;
+  int32_t reorth;        /* Lanczos (Algorithm 2): PHIPM_REORTH_LOCAL (default) applies
+                            classical Gram-Schmidt twice against the two previous basis
+                            vectors; PHIPM_REORTH_FULL against all of them (the Arnoldi
+                            process on a symmetric matrix; eq. 4 then prices the step as
+                            Arnoldi).  No effect on Arnoldi. */
+  int32_t fp32_flags;    /* FP32 basis only: PHIPM_FP32_ONLY builds every step in FP32
+                            whatever its rounding estimate (diagnostics: the true error
+                            of the FP32 basis).  Default 0. */
   int32_t pad_;
 } phipm_opts;
+
+enum { PHIPM_REORTH_LOCAL = 0, PHIPM_REORTH_FULL = 1 };
+enum { PHIPM_FP32_ONLY = 1 };
 
 #define PHIPM_M_CAP 128
 #define PHIPM_P_MAX 8
@@ -116,15 +133,19 @@ typedef struct {
   double bytes;      /* algorithmic HBM bytes of the streaming phases: every CSR array,
                         basis column and vector counted once per pass that touches it */
   double phi_ratio_max;        /* FP32 basis: largest ||beta y||_2 / ||u_k||_2 of a step */
-  int64_t precision_rejects;   /* FP32 basis: attempts rejected for basis rounding */
-  double fp32_error_estimate;  /* FP32 basis: accumulated absolute rounding estimate of the
-                                  FP32 phi-parts (of the FP32 run, if it fell back) */
-  int32_t fp64_fallback;       /* FP32 basis: 1 if the estimate exceeded 2 tol max(1, ||u||)
-                                  and the solve was repeated with the FP64 basis; the
-                                  counters then include both runs */
+  int64_t precision_rejects;   /* FP32 basis: FP32 attempts accepted by the error estimate
+                                  but repeated with the FP64 basis (rounding over budget) */
+  double fp32_error_estimate;  /* FP32 basis: summed absolute rounding estimates
+                                  eps32 ||beta y||_2 of the FP32 steps */
+  int32_t fp64_steps;          /* FP32 basis: accepted steps built with the FP64 basis */
   int32_t trace_len;           /* accepted steps offered to the trace (records beyond
                                   trace_cap are dropped) */
   int64_t proposals;           /* steps seeded by the proposer */
+  double bytes_ref;            /* the same work priced by the reference byte model of a
+                                  plain CGS2 Krylov step: per basis vector j+1 (0-based j)
+                                  the CSR product plus (4(j+1) + 8) vectors (Arnoldi) or
+                                  16 vectors (Lanczos); per step p products and 3p vectors
+                                  for eq. wrecurrence and (p + m + 2) vectors for eq. step */
 } phipm_stats;
 
 void phipm_default_opts(phipm_opts* opts);

@@ -22,13 +22,19 @@ _SRC = os.path.join(_HERE, "phipm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
+# -O3 for an x86-64 baseline with AVX2 (every current server CPU; the library
+# is built once and may run on another host); no contraction of a*b + c into
+# fused multiply-adds, so the arithmetic is the plain one the source spells
+# out on every machine.
+CFLAGS = ["-O3", "-march=x86-64-v3", "-ffp-contract=off", "-std=c11", "-D_GNU_SOURCE",
+          "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP)."""
+    """Compile the oracle with gcc (OpenMP; CFLAGS)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
-             "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -98,6 +104,8 @@ def lib():
         L.oracle_default_opts.argtypes = [C.POINTER(Opts)]
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = None
         L.oracle_phi.argtypes = [C.c_int, C.c_double]
         L.oracle_phi.restype = C.c_double
         L.oracle_expm.argtypes = [C.c_int, _dp, _dp]
@@ -254,6 +262,11 @@ def decide(state: Alg4State, **attempt):
 
 def threads() -> int:
     return lib().oracle_threads()
+
+
+def set_threads(k: int) -> None:
+    """Threads of the OpenMP loops from now on (results do not depend on it)."""
+    lib().oracle_set_threads(int(k))
 
 
 def phipm(t, A, b, opts: Opts | None = None, trace_cap: int = 0, allow_limit: bool = False,

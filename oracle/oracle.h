@@ -43,15 +43,17 @@ extern "C" {
 #endif
 
 /* Krylov flavours.  Arnoldi: 0 = modified Gram-Schmidt exactly as Algorithm 1,
- * 1 = classical Gram-Schmidt applied twice (CGS2).  Lanczos: 0 = three-term
+ * 1 or 2 = classical Gram-Schmidt applied twice (CGS2).  Lanczos: 0 = three-term
  * recurrence of Algorithm 2 (indices read as the standard recurrence), 1 = CGS2
- * against the two previous basis vectors only. */
+ * against the two previous basis vectors only, 2 = CGS2 against all previous
+ * basis vectors (full reorthogonalisation; the step is then priced by eq. 4 as
+ * Arnoldi's). */
 typedef struct {
   double  tol;        /* absolute tolerance Tol of eq. taunew (default 1e-7) */
   int32_t symm;       /* -1 detect exactly, 0 Arnoldi, 1 Lanczos */
   int32_t m_init;     /* initial Krylov dimension (Algorithm 3: 10) */
   int32_t m_max;      /* largest Krylov dimension (default 100) */
-  int32_t reorth;     /* 1 = CGS2 flavour (default), 0 = as printed */
+  int32_t reorth;     /* 1 = CGS2 flavour (default), 0 = as printed, 2 = full CGS2 */
   int32_t adapt_m;    /* 1 = adapt m (phipm), 0 = keep m fixed (phip) */
   int32_t corrector;  /* 1 = use eq. phipapprox2 (default), 0 = eq. phipapprox */
   int32_t pad_;
@@ -77,8 +79,9 @@ enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_EMAXSTEPS = -5, ORACLE_ENONFINI
 
 void   oracle_default_opts(oracle_opts* o);
 
-/* threads the OpenMP loops use */
+/* threads the OpenMP loops use; set_threads changes it (k >= 1) */
 int    oracle_threads(void);
+void   oracle_set_threads(int k);
 
 /* scalar phi_k(z), k >= 0 */
 double oracle_phi(int k, double z);

@@ -44,6 +44,14 @@ int oracle_threads(void) {
 #endif
 }
 
+void oracle_set_threads(int k) {
+#ifdef _OPENMP
+  if (k >= 1) omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
+}
+
 /* ------------------------------------------------------- scalar phi_k(z) */
 
 /* Eq. phifunctions.  Small |z|: the power series phi_k(z) = sum_i z^i/(i+k)!
@@ -262,8 +270,9 @@ static double krylov_step(int n, const int32_t* rp, const int32_t* ci, const dou
     axpy(n, -a, vj, w);
   } else {
     /* CGS2: classical Gram-Schmidt twice.  Lanczos restricts the projection
-     * to the two most recent basis vectors. */
-    int i0 = lanczos ? (j > 0 ? j - 1 : 0) : 0;
+     * to the two most recent basis vectors (reorth = 1) or projects against
+     * all of them like Arnoldi (reorth = 2, full reorthogonalisation). */
+    int i0 = (lanczos && reorth == 1) ? (j > 0 ? j - 1 : 0) : 0;
     double c[1024];
     for (int i = i0; i <= j; ++i) H[i * ldh + j] = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -664,7 +673,9 @@ int oracle_phipm(double t_end, int n, const int32_t* rp, const int32_t* ci, cons
         memset(&at, 0, sizeof(at));
         at.tau = tau; at.eps = eps; at.omega = omega; at.knorm = knorm; at.rem = t_end - t;
         at.nnz = (double)nnz; at.n = (double)n;
-        at.m_use = m_use; at.m_req = m; at.m_cap = m_cap; at.lanczos = lanczos; at.p = p;
+        /* eq. 4 prices the work done: full reorthogonalisation is Arnoldi's */
+        at.m_use = m_use; at.m_req = m; at.m_cap = m_cap; at.p = p;
+        at.lanczos = lanczos && o->reorth != 2;
         at.adapt_m = o->adapt_m; at.broke = broke; at.tau_fixed = o->tau_fixed > 0.0;
         oracle_decision dc;
         oracle_decide(&as, &at, &dc);

@@ -6,8 +6,11 @@ binding raises if that library is missing; there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -16,6 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libphipm.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EMAXSTEPS, EUNSUPPORTED, EABORT = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_BASIS = 0, 1
+F64, F32 = 0, 1                        # CSR value types (phipm_csr.val_dtype)
+REORTH_LOCAL, REORTH_FULL = 0, 1
+FP32_ONLY = 1
 M_CAP, P_MAX = 128, 8
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 12, 64, 2, 5122
 
@@ -29,7 +35,8 @@ class PhipmError(RuntimeError):
 
 class CSR(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p),
-                ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+                ("col_idx", C.c_void_p), ("val", C.c_void_p), ("val_dtype", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class Opts(C.Structure):
@@ -38,7 +45,8 @@ class Opts(C.Structure):
                 ("corrector", C.c_int32), ("tau_fixed", C.c_double),
                 ("max_attempts", C.c_int64), ("workgroups", C.c_int32),
                 ("validate", C.c_int32), ("proposer", C.c_void_p), ("history", C.c_void_p),
-                ("trace", C.c_void_p), ("trace_cap", C.c_int32), ("pad_", C.c_int32)]
+                ("trace", C.c_void_p), ("trace_cap", C.c_int32), ("reorth", C.c_int32),
+                ("fp32_flags", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -48,8 +56,8 @@ class Stats(C.Structure):
                 ("workgroups", C.c_int32), ("anorm", C.c_double), ("setup_flags", C.c_int32),
                 ("pad_", C.c_int32), ("bytes", C.c_double), ("phi_ratio_max", C.c_double),
                 ("precision_rejects", C.c_int64), ("fp32_error_estimate", C.c_double),
-                ("fp64_fallback", C.c_int32), ("trace_len", C.c_int32),
-                ("proposals", C.c_int64)]
+                ("fp64_steps", C.c_int32), ("trace_len", C.c_int32),
+                ("proposals", C.c_int64), ("bytes_ref", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -194,22 +202,28 @@ def _stream_ptr(stream=None):
 
 
 class DeviceCSR:
-    """A CSR matrix resident on the GPU (int32 indices, float64 values)."""
+    """A CSR matrix resident on the GPU (int32 indices; float64 values, or
+    float32 with dtype=np.float32, which the solver then reads as they are:
+    the matrix is the float32-rounded one)."""
 
-    def __init__(self, A, device="cuda"):
+    def __init__(self, A, device="cuda", dtype=np.float64):
         torch = _torch()
+        dtype = np.dtype(dtype)
+        if dtype not in (np.dtype(np.float64), np.dtype(np.float32)):
+            raise ValueError("CSR values must be float64 or float32")
+        self.val_dtype = F32 if dtype == np.float32 else F64
         self.n = int(A.shape[0])
         self.nnz = int(A.nnz)
         self.row_ptr = torch.as_tensor(np.asarray(A.indptr, dtype=np.int32), device=device)
         self.col_idx = torch.as_tensor(np.asarray(A.indices, dtype=np.int32), device=device)
-        self.val = torch.as_tensor(np.asarray(A.data, dtype=np.float64), device=device)
+        self.val = torch.as_tensor(np.asarray(A.data, dtype=dtype), device=device)
         if self.nnz == 0:   # keep non-null pointers
             self.col_idx = torch.zeros(1, dtype=torch.int32, device=device)
-            self.val = torch.zeros(1, dtype=torch.float64, device=device)
+            self.val = torch.zeros(1, dtype=self.val.dtype, device=device)
 
     def c(self) -> CSR:
         return CSR(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
-                   self.val.data_ptr())
+                   self.val.data_ptr(), self.val_dtype, 0)
 
 
 def workspace_bytes(A: DeviceCSR, p: int, opts: Opts) -> int:
@@ -364,6 +378,7 @@ class Plan:
         if rc != OK:
             raise PhipmError(rc, "phipm_plan_create")
         self._h = h
+        _LIVE_PLANS.add(self)
 
     def execute(self, stream=None):
         rc = lib().phipm_plan_execute(self._h, _stream_ptr(stream))
@@ -388,10 +403,30 @@ class Plan:
         if getattr(self, "_h", None):
             lib().phipm_plan_destroy(self._h)
             self._h = None
+        _LIVE_PLANS.discard(self)
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down: live plans are
+        # released by _close_live_plans() while the runtime is still up
+        if sys.is_finalizing():
+            return
         try:
             self.close()
+        except Exception:
+            pass
+
+
+# Plans still open when the interpreter exits are released by an atexit
+# handler, which runs before the C-level exit handlers tear down the HIP
+# runtime (and any profiler attached to it).
+_LIVE_PLANS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_plans():
+    for pl in list(_LIVE_PLANS):
+        try:
+            pl.close()
         except Exception:
             pass
 

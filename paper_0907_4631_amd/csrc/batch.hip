@@ -34,11 +34,11 @@ namespace {
 struct Inst {
   const int* rp;
   const int* ci;
-  const double* val;
+  const void* val;  // of the plan's value type (every instance has the same)
   const double* b;
   double* u;
   double t;
-  int n, nnz, p, pad;
+  int n, nnz, p, val32;
 };
 
 // One team (device array).
@@ -66,7 +66,8 @@ struct BatchArgs {
   double* hpool;      // [grid] copies of H, one per workgroup
   double tol, tau_fixed;
   long long max_attempts;
-  int ncls, symm, m_init, m_max, adapt_m, corrector, validate, pad;
+  int ncls, symm, m_init, m_max, adapt_m, corrector, validate, full_reorth;
+  int fp32_flags, pad;
   unsigned long long spin;
   const float* proposer;
 };
@@ -96,7 +97,10 @@ __global__ __launch_bounds__(256) void k_inst_norms(const Inst* inst, double* ou
     k0 = k0 < 0 ? 0 : (k0 > in.nnz ? in.nnz : k0);
     k1 = k1 < k0 ? k0 : (k1 > in.nnz ? in.nnz : k1);
     double s = 0.0;
-    for (int k = k0; k < k1; ++k) s += fabs(in.val[k]);
+    if (in.val32)
+      for (int k = k0; k < k1; ++k) s += fabs((double)static_cast<const float*>(in.val)[k]);
+    else
+      for (int k = k0; k < k1; ++k) s += fabs(static_cast<const double*>(in.val)[k]);
     mx = nanmax(mx, s);
   }
   mx = wave_max(mx);
@@ -109,7 +113,8 @@ __global__ __launch_bounds__(256) void k_inst_norms(const Inst* inst, double* ou
   }
 }
 
-template <typename T>
+// T: basis type, VT: CSR value type.
+template <typename T, typename VT>
 __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
   __shared__ Shared sh;
   const int ti = a.team_of[blockIdx.x];
@@ -132,7 +137,6 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
     w.ex = reinterpret_cast<double*>(base + a.wl.ex);
     w.st = reinterpret_cast<State*>(base + a.wl.st);
   }
-  float* val32 = reinterpret_cast<float*>(a.ws + tr.ws + a.wl.val32);
   int qc = tr.cls;  // queue the team leader takes from next (used by rank 0 only)
   for (;;) {
     // the leader takes the next instance (-1: none left); the other members
@@ -159,7 +163,6 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
     P.rp = in.rp;
     P.ci = in.ci;
     P.val = in.val;
-    P.val32 = val32;
     P.b = in.b;
     P.ldb = in.n;
     P.u = in.u;
@@ -173,19 +176,32 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
     P.adapt_m = a.adapt_m;
     P.corrector = a.corrector;
     P.validate = a.validate;
+    P.full_reorth = a.full_reorth;
+    P.fp32_flags = a.fp32_flags;
     P.proposer = a.proposer;
     w.stats = a.stats + id;
     if (rank == 0 && threadIdx.x == 0) a.clk[2 * id] = wall_clock64();
-    solve_mixed<T>(tm, P, w, sh);
+    solve<T, VT>(tm, P, w, sh);
     if (rank == 0 && threadIdx.x == 0) a.clk[2 * id + 1] = wall_clock64();
   }
 }
 
 // ------------------------------------------------------------ host side
 
+// The batched kernel of a (basis, values) type pair: index 2 * fp32 basis +
+// float32 values.
+const void* batch_kernel(int idx) {
+  switch (idx) {
+    case 0: return reinterpret_cast<const void*>(k_batch<double, double>);
+    case 1: return reinterpret_cast<const void*>(k_batch<double, float>);
+    case 2: return reinterpret_cast<const void*>(k_batch<float, double>);
+    default: return reinterpret_cast<const void*>(k_batch<float, float>);
+  }
+}
+
 struct BatchDevice {
   int cus = 0;
-  int coresident[2] = {0, 0};  // float64, float32 basis
+  int coresident[4] = {0, 0, 0, 0};  // per batch_kernel() index
   unsigned long long spin_ticks = 0;
   double clock_hz = 1e8;
   bool ok = false;
@@ -203,13 +219,13 @@ const BatchDevice* batch_device() {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return nullptr;
     d.cus = prop.multiProcessorCount;
-    int b64 = 0, b32 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b64, k_batch<double>, BLOCK, 0) !=
-            hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, k_batch<float>, BLOCK, 0) != hipSuccess)
-      return nullptr;
-    d.coresident[0] = std::min(TEAM_MAX, std::max(1, b64) * d.cus);
-    d.coresident[1] = std::min(TEAM_MAX, std::max(1, b32) * d.cus);
+    for (int k = 0; k < 4; ++k) {
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_kernel(k), BLOCK, 0) !=
+          hipSuccess)
+        return nullptr;
+      d.coresident[k] = std::min(TEAM_MAX, std::max(1, b) * d.cus);
+    }
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
       khz = 100000;
@@ -335,6 +351,7 @@ struct phipm_plan {
   int device = 0;
   int count = 0;
   bool fp32 = false;
+  int kidx = 0;  // batch_kernel() index
   int grid = 0;
   phipm_opts opts{};
   std::vector<Inst> inst;
@@ -426,6 +443,8 @@ int set_layout(phipm_plan* pl, const TeamLayout& L, hipStream_t stream) {
   a.adapt_m = pl->opts.adapt_m;
   a.corrector = pl->opts.corrector;
   a.validate = pl->opts.validate;
+  a.full_reorth = pl->opts.reorth == PHIPM_REORTH_FULL;
+  a.fp32_flags = pl->fp32 ? pl->opts.fp32_flags : 0;
   a.spin = pl->spin;
   a.proposer = pl->opts.proposer;
   pl->layout = L;
@@ -440,8 +459,7 @@ hipError_t launch_reset(phipm_plan* pl, hipStream_t stream) {
 
 hipError_t launch_batch(phipm_plan* pl, hipStream_t stream, bool cooperative) {
   void* args[] = {&pl->args};
-  const void* fn = pl->fp32 ? reinterpret_cast<const void*>(k_batch<float>)
-                            : reinterpret_cast<const void*>(k_batch<double>);
+  const void* fn = batch_kernel(pl->kidx);
   if (cooperative)
     return hipLaunchCooperativeKernel(fn, dim3(pl->grid), dim3(BLOCK), args, 0, stream);
   return hipLaunchKernel(fn, dim3(pl->grid), dim3(BLOCK), args, 0, stream);
@@ -630,14 +648,14 @@ int phipm_plan_create(int count, const phipm_csr* A, const int32_t* p, const dou
   *out = nullptr;
   if (count < 1 || !A || !p || !t || !b || !u || !opts_ok(o) || !po) return PHIPM_EINVAL;
   if (po->max_team < 0 || (po->max_team & (po->max_team - 1)) != 0) return PHIPM_EINVAL;
-  int nmax = 1, nnzmax = 1, pmax = 0;
+  int nmax = 1, pmax = 0;
   for (int i = 0; i < count; ++i) {
     if (!csr_ok(&A[i]) || p[i] < 0 || p[i] > PHIPM_P_MAX || !b[i] || !u[i]) return PHIPM_EINVAL;
+    if (A[i].val_dtype != A[0].val_dtype) return PHIPM_EINVAL;  // one value type per plan
     if (!std::isfinite(t[i])) return PHIPM_ENONFINITE;
     const size_t ub = sizeof(double) * (size_t)A[i].n;
     if (overlaps(u[i], ub, b[i], ub * (size_t)(p[i] + 1))) return PHIPM_EINVAL;
     nmax = std::max(nmax, A[i].n);
-    nnzmax = std::max(nnzmax, A[i].nnz);
     pmax = std::max(pmax, (int)p[i]);
   }
   // outputs must not overlap each other
@@ -658,7 +676,8 @@ int phipm_plan_create(int count, const phipm_csr* A, const int32_t* p, const dou
   pl->count = count;
   pl->opts = *o;
   pl->fp32 = o->precision == PHIPM_FP32_BASIS;
-  const int gmax = d->coresident[pl->fp32 ? 1 : 0];
+  pl->kidx = 2 * pl->fp32 + (A[0].val_dtype == PHIPM_F32);
+  const int gmax = d->coresident[pl->kidx];
   pl->grid = o->workgroups > 0 ? std::min(o->workgroups, gmax) : gmax;
   pl->spin = d->spin_ticks;
   pl->clock_hz = d->clock_hz;
@@ -674,11 +693,11 @@ int phipm_plan_create(int count, const phipm_csr* A, const int32_t* p, const dou
     in.n = A[i].n;
     in.nnz = A[i].nnz;
     in.p = p[i];
-    in.pad = 0;
+    in.val32 = A[i].val_dtype == PHIPM_F32;
   }
   // one allocation for everything the plan keeps on the device
   const int G = pl->grid;
-  pl->wl = work_layout(nmax, nnzmax, pmax, std::min(o->m_max, nmax), pl->fp32, 0);
+  pl->wl = work_layout(nmax, pmax, std::min(o->m_max, nmax), 0);
   pl->team_ws = pl->wl.total;
   pl->nflags = (size_t)FLAG_STRIDE * 3 * (size_t)G;
   // >= sum over teams of team_partials(size) + KMAX (teams of one: 1 + TEAM_GBUF + 1 rows)

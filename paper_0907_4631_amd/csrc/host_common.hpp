@@ -19,6 +19,7 @@ static_assert(sizeof(Stats) == sizeof(phipm_stats), "Stats mirrors phipm_stats")
 static_assert(sizeof(TraceStep) == sizeof(phipm_trace_step), "TraceStep mirrors phipm_trace_step");
 static_assert(offsetof(TraceStep, H) == offsetof(phipm_trace_step, H), "trace layout");
 static_assert(offsetof(Stats, proposals) == offsetof(phipm_stats, proposals), "stats layout");
+static_assert(offsetof(Stats, bytes_ref) == offsetof(phipm_stats, bytes_ref), "stats layout");
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 inline long long pad64(long long x) { return (x + 63) / 64 * 64; }
@@ -27,15 +28,15 @@ inline long long pad64(long long x) { return (x + 63) / 64 * 64; }
 // instance except its barrier flags and reduction partials).
 struct WorkLayout {
   long long ld;      // leading dimension of W and V (rows padded to 64)
-  size_t W, V, y0, y1, val32, H, ex, st, stats, total;
+  size_t W, V, y0, y1, H, ex, st, stats, total;
 };
 
 // The basis and its two work vectors are sized for float64 also with the
-// FP32 basis, which falls back to the FP64 basis in the same buffer when its
-// rounding estimate runs over budget.
+// FP32 basis: a step whose FP32 rounding would not fit the tolerance is
+// built with the FP64 basis in the same buffer.
 // hcopies: copies of H (one per workgroup of the launch; 0 when the caller
 // places them elsewhere).
-inline WorkLayout work_layout(int n, int nnz, int p, int m_cap, bool fp32, int hcopies) {
+inline WorkLayout work_layout(int n, int p, int m_cap, int hcopies) {
   WorkLayout L{};
   const size_t tb = 8;
   L.ld = pad64(n);
@@ -45,7 +46,6 @@ inline WorkLayout work_layout(int n, int nnz, int p, int m_cap, bool fp32, int h
   L.V = take(tb * (size_t)L.ld * (size_t)(m_cap + 1));
   L.y0 = take(tb * (size_t)L.ld);
   L.y1 = take(tb * (size_t)L.ld);
-  L.val32 = take(fp32 ? sizeof(float) * (size_t)std::max(nnz, 1) : 0);
   L.H = take(sizeof(double) * H_WORDS * (size_t)hcopies);
   L.ex = take(sizeof(double) * 8 * (size_t)NMAX_EXPM * NMAX_EXPM);
   L.st = take(sizeof(State));
@@ -68,11 +68,14 @@ inline bool opts_ok(const phipm_opts* o) {
          o->m_max <= PHIPM_M_CAP && (o->symm >= -1 && o->symm <= 1) &&
          (o->precision == PHIPM_FP64 || o->precision == PHIPM_FP32_BASIS) && o->max_attempts >= 1 &&
          o->workgroups >= 0 && std::isfinite(o->tau_fixed) && o->tau_fixed >= 0.0 &&
-         o->trace_cap >= 0 && (o->trace_cap == 0 || o->trace);
+         o->trace_cap >= 0 && (o->trace_cap == 0 || o->trace) &&
+         (o->reorth == PHIPM_REORTH_LOCAL || o->reorth == PHIPM_REORTH_FULL) &&
+         (o->fp32_flags & ~PHIPM_FP32_ONLY) == 0;
 }
 
 inline bool csr_ok(const phipm_csr* A) {
-  return A && A->n > 0 && A->nnz >= 0 && A->row_ptr && (A->nnz == 0 || (A->col_idx && A->val));
+  return A && A->n > 0 && A->nnz >= 0 && A->row_ptr && (A->nnz == 0 || (A->col_idx && A->val)) &&
+         (A->val_dtype == PHIPM_F64 || A->val_dtype == PHIPM_F32);
 }
 
 inline bool overlaps(const void* a, size_t na, const void* c, size_t nc) {
@@ -99,9 +102,10 @@ inline void copy_stats(const Stats& hs, int status, phipm_stats* s) {
   s->phi_ratio_max = hs.rho_max;
   s->precision_rejects = hs.prec_rejects;
   s->fp32_error_estimate = hs.fp32_err;
-  s->fp64_fallback = hs.fp64_fallback;
+  s->fp64_steps = hs.fp64_steps;
   s->trace_len = hs.trace_len;
   s->proposals = hs.proposals;
+  s->bytes_ref = hs.bytes_ref;
 }
 
 }  // namespace pkr

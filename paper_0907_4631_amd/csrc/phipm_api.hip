@@ -22,7 +22,8 @@ __global__ void k_zero_ctl(TeamCtl* ctl, int count) {
 }
 
 // One 1024-thread workgroup per CU (16 waves, at most 128 VGPRs each).
-template <typename T>
+// T: basis type, VT: CSR value type.
+template <typename T, typename VT>
 __global__ __launch_bounds__(BLOCK) void k_solve(Problem P, Work<T> w, TeamCtl* ctl,
                                                  double* partials, double* result,
                                                  unsigned long long spin) {
@@ -31,16 +32,28 @@ __global__ __launch_bounds__(BLOCK) void k_solve(Problem P, Work<T> w, TeamCtl* 
                             result, spin);
   Work<T> wk = w;
   wk.Hm = w.H + (size_t)blockIdx.x * H_WORDS;
-  solve_mixed<T>(tm, P, wk, sh);
+  solve<T, VT>(tm, P, wk, sh);
 }
 
+// The solver kernel of a (basis, values) type pair: index 2 * fp32 basis +
+// float32 values.
+const void* solve_kernel(int idx) {
+  switch (idx) {
+    case 0: return reinterpret_cast<const void*>(k_solve<double, double>);
+    case 1: return reinterpret_cast<const void*>(k_solve<double, float>);
+    case 2: return reinterpret_cast<const void*>(k_solve<float, double>);
+    default: return reinterpret_cast<const void*>(k_solve<float, float>);
+  }
+}
+
+template <typename VT>
 __global__ __launch_bounds__(BLOCK) void k_spmv(int n, const int* rp, const int* ci,
-                                                const double* val, const double* x, double* y) {
-  __shared__ SpmvSmem<double> sm;
+                                                const VT* val, const double* x, double* y) {
+  __shared__ SpmvSmem<VT> sm;
   auto ld = [&](int c) -> double { return x[c]; };
   for (long long r0 = (long long)blockIdx.x * BLOCK; r0 < n; r0 += (long long)gridDim.x * BLOCK) {
     const int r1 = (int)std::min<long long>(r0 + BLOCK, n);
-    double acc = spmv_tile<double, double>(rp, ci, val, (int)r0, r1, sm, ld);
+    double acc = spmv_tile<VT, double>(rp, ci, val, (int)r0, r1, sm, ld);
     const int r = (int)r0 + threadIdx.x;
     if (r < r1) y[r] = acc;
   }
@@ -98,6 +111,7 @@ __global__ __launch_bounds__(BLOCK) void k_krylov(Problem P, Work<double> w0, co
                             result, spin);
   Work<double> w = w0;
   w.Hm = w0.H + (size_t)blockIdx.x * H_WORDS;
+  const double* val = static_cast<const double*>(P.val);
   int rb, re;
   own_rows(tm, P.n, rb, re);
   // the column range of the own rows: every slot (this entry point skips
@@ -117,10 +131,10 @@ __global__ __launch_bounds__(BLOCK) void k_krylov(Problem P, Work<double> w0, co
   KrylovCtl kc{0, 1, 0, 1};
   while (!kc.broke && kc.have < m && kc.have < P.n) {
     const bool ok = kc.have == 0
-                        ? krylov_iter<double, double>(tm, P, w, P.val, 1.0, lanczos != 0, 0.0, kc,
-                                                      v, 1.0 / beta, rb, re, sh)
-                        : krylov_iter<double, double>(tm, P, w, P.val, 1.0, lanczos != 0, 0.0, kc,
-                                                      nullptr, 0.0, rb, re, sh);
+                        ? krylov_iter<double, double, double>(tm, P, w, val, 1.0, lanczos != 0,
+                                                              0.0, kc, v, 1.0 / beta, rb, re, sh)
+                        : krylov_iter<double, double, double>(tm, P, w, val, 1.0, lanczos != 0,
+                                                              0.0, kc, nullptr, 0.0, rb, re, sh);
     if (!ok) return;
   }
   if (!krylov_finalize<double>(tm, P, w, lanczos != 0, 0.0, kc, rb, re, sh)) return;
@@ -138,8 +152,7 @@ __global__ __launch_bounds__(BLOCK) void k_krylov(Problem P, Work<double> w0, co
 
 struct DeviceInfo {
   int cus = 0;
-  int coresident64 = 0;  // cooperative grid limit for the float64 solver
-  int coresident32 = 0;
+  int coresident[4] = {0, 0, 0, 0};  // cooperative grid limit per solve_kernel() index
   unsigned long long spin_ticks = 0;
   bool ok = false;
 };
@@ -156,13 +169,13 @@ const DeviceInfo* device_info() {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return nullptr;
     d.cus = prop.multiProcessorCount;
-    int b64 = 0, b32 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b64, k_solve<double>, BLOCK, 0) != hipSuccess)
-      return nullptr;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b32, k_solve<float>, BLOCK, 0) != hipSuccess)
-      return nullptr;
-    d.coresident64 = std::min(TEAM_MAX, std::max(1, b64) * d.cus);
-    d.coresident32 = std::min(TEAM_MAX, std::max(1, b32) * d.cus);
+    for (int k = 0; k < 4; ++k) {
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, solve_kernel(k), BLOCK, 0) !=
+          hipSuccess)
+        return nullptr;
+      d.coresident[k] = std::min(TEAM_MAX, std::max(1, b) * d.cus);
+    }
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
       khz = 100000;
@@ -179,9 +192,9 @@ struct Layout {
   size_t ctl, part, res, total;
 };
 
-Layout layout(int n, int nnz, int p, int m_cap, bool fp32, int gmax, int groups) {
+Layout layout(int n, int p, int m_cap, int gmax, int groups) {
   Layout L{};
-  L.w = work_layout(n, nnz, p, m_cap, fp32, groups);
+  L.w = work_layout(n, p, m_cap, groups);
   size_t off = L.w.total;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   L.ctl = take(sizeof(TeamCtl));
@@ -241,10 +254,10 @@ int phipm_workspace_bytes(const phipm_csr* A, int p, const phipm_opts* o, size_t
   if (!csr_ok(A) || p < 0 || p > PHIPM_P_MAX || !opts_ok(o) || !bytes) return PHIPM_EINVAL;
   const DeviceInfo* d = device_info();
   if (!d) return PHIPM_EHIP;
-  const bool fp32 = o->precision == PHIPM_FP32_BASIS;
-  const int gmax = fp32 ? d->coresident32 : d->coresident64;
+  const int kidx = 2 * (o->precision == PHIPM_FP32_BASIS) + (A->val_dtype == PHIPM_F32);
+  const int gmax = d->coresident[kidx];
   const int m_cap = std::min(o->m_max, A->n);
-  *bytes = layout(A->n, A->nnz, p, m_cap, fp32, gmax, choose_workgroups(o, A->n, gmax)).total;
+  *bytes = layout(A->n, p, m_cap, gmax, choose_workgroups(o, A->n, gmax)).total;
   return PHIPM_OK;
 }
 
@@ -258,10 +271,11 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   const DeviceInfo* d = device_info();
   if (!d) return fail(PHIPM_EHIP);
   const bool fp32 = o->precision == PHIPM_FP32_BASIS;
-  const int gmax = fp32 ? d->coresident32 : d->coresident64;
+  const int kidx = 2 * fp32 + (A->val_dtype == PHIPM_F32);
+  const int gmax = d->coresident[kidx];
   const int m_cap = std::min(o->m_max, A->n);
   const int G = choose_workgroups(o, A->n, gmax);
-  const Layout L = layout(A->n, A->nnz, p, m_cap, fp32, gmax, G);
+  const Layout L = layout(A->n, p, m_cap, gmax, G);
   if (ws_bytes < L.total) return fail(PHIPM_ENOMEM);
   // u must not overlap b or the workspace
   const size_t ub = sizeof(double) * (size_t)A->n;
@@ -276,7 +290,6 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   P.rp = A->row_ptr;
   P.ci = A->col_idx;
   P.val = A->val;
-  P.val32 = reinterpret_cast<float*>(ws + L.w.val32);
   P.b = b;
   P.ldb = A->n;
   P.u = u;
@@ -290,6 +303,8 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   P.adapt_m = o->adapt_m;
   P.corrector = o->corrector;
   P.validate = o->validate;
+  P.full_reorth = o->reorth == PHIPM_REORTH_FULL;
+  P.fp32_flags = fp32 ? o->fp32_flags : 0;
   P.proposer = o->proposer;
   P.history = o->history;
   P.trace = static_cast<TraceStep*>(o->trace);
@@ -307,13 +322,11 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   if (fp32) {
     Work<float> w = work_at<float>(ws, L.w);
     void* args[] = {&P, &w, &ctl, &part, &res, &spin};
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_solve<float>), dim3(G),
-                                   dim3(BLOCK), args, 0, stream);
+    e = hipLaunchCooperativeKernel(solve_kernel(kidx), dim3(G), dim3(BLOCK), args, 0, stream);
   } else {
     Work<double> w = work_at<double>(ws, L.w);
     void* args[] = {&P, &w, &ctl, &part, &res, &spin};
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_solve<double>), dim3(G),
-                                   dim3(BLOCK), args, 0, stream);
+    e = hipLaunchCooperativeKernel(solve_kernel(kidx), dim3(G), dim3(BLOCK), args, 0, stream);
   }
   if (e != hipSuccess) return fail(PHIPM_EHIP);
   t_last_stream = stream;
@@ -354,8 +367,12 @@ int phipm_spmv(const phipm_csr* A, const double* x, double* y, phipm_stream_t st
   if (!d) return PHIPM_EHIP;
   const long long tiles = ((long long)A->n + BLOCK - 1) / BLOCK;
   const int grid = (int)std::min<long long>(tiles, (long long)d->cus * 8);
-  hipLaunchKernelGGL(k_spmv, dim3(grid), dim3(BLOCK), 0, stream, A->n, A->row_ptr, A->col_idx,
-                     A->val, x, y);
+  if (A->val_dtype == PHIPM_F32)
+    hipLaunchKernelGGL(k_spmv<float>, dim3(grid), dim3(BLOCK), 0, stream, A->n, A->row_ptr,
+                       A->col_idx, static_cast<const float*>(A->val), x, y);
+  else
+    hipLaunchKernelGGL(k_spmv<double>, dim3(grid), dim3(BLOCK), 0, stream, A->n, A->row_ptr,
+                       A->col_idx, static_cast<const double*>(A->val), x, y);
   return hipGetLastError() == hipSuccess ? PHIPM_OK : PHIPM_EHIP;
 }
 
@@ -363,7 +380,8 @@ int phipm_allen_cahn_update(const phipm_csr* L, double* u, const double* du,
                             const int32_t* diag_pos, const double* lap_diag, double* J_val,
                             double* F, phipm_stream_t stream_) {
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  if (!csr_ok(L) || !u || (J_val && (!diag_pos || !lap_diag))) return PHIPM_EINVAL;
+  if (!csr_ok(L) || L->val_dtype != PHIPM_F64 || !u || (J_val && (!diag_pos || !lap_diag)))
+    return PHIPM_EINVAL;
   const DeviceInfo* d = device_info();
   if (!d) return PHIPM_EHIP;
   const long long tiles = ((long long)L->n + BLOCK - 1) / BLOCK;
@@ -376,7 +394,8 @@ int phipm_allen_cahn_update(const phipm_csr* L, double* u, const double* du,
   if (F || J_val) {
     const int grid = (int)std::min<long long>(std::max<long long>(tiles, 1), (long long)d->cus * 8);
     hipLaunchKernelGGL(k_allen_cahn, dim3(grid), dim3(BLOCK), 0, stream, L->n, L->row_ptr,
-                       L->col_idx, L->val, u, diag_pos, lap_diag, J_val, F);
+                       L->col_idx, static_cast<const double*>(L->val), u, diag_pos, lap_diag,
+                       J_val, F);
     if (hipGetLastError() != hipSuccess) return PHIPM_EHIP;
   }
   return PHIPM_OK;
@@ -392,15 +411,16 @@ int phipm_expm(int N, const double* H, double* E, double* scratch, phipm_stream_
 int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double* V, double* H,
                  void* workspace, size_t ws_bytes, int* m_done, phipm_stream_t stream_) {
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  if (!csr_ok(A) || !v || !V || !H || !workspace || !m_done || m < 1 || m > PHIPM_M_CAP)
+  if (!csr_ok(A) || A->val_dtype != PHIPM_F64 || !v || !V || !H || !workspace || !m_done ||
+      m < 1 || m > PHIPM_M_CAP)
     return PHIPM_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return PHIPM_EINVAL;
   const DeviceInfo* d = device_info();
   if (!d) return PHIPM_EHIP;
   phipm_opts o;
   phipm_default_opts(&o);
-  const int G = choose_workgroups(&o, A->n, d->coresident64);
-  const Layout L = layout(A->n, A->nnz, 0, m, false, d->coresident64, G);
+  const int G = choose_workgroups(&o, A->n, d->coresident[0]);
+  const Layout L = layout(A->n, 0, m, d->coresident[0], G);
   if (ws_bytes < L.total) return PHIPM_ENOMEM;
   char* ws = static_cast<char*>(workspace);
   Problem P{};

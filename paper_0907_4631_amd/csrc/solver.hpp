@@ -17,7 +17,6 @@
 //   W            n x p      float64   w_1..w_p of eq. wrecurrence
 //   V            n x (m+1)  T         Krylov basis
 //   y0, y1       n          T         the candidate u and the product w of a Krylov step
-//   val32        nnz        float     CSR values rounded to float (T = float)
 //   H            (M_CAP+1) x M_CAP float64, row-major, one copy per workgroup
 //                                     (workgroup 0's feeds the exponential)
 //   ex           8 (m+p+1)^2 float64, the small exponential's scratch
@@ -42,8 +41,7 @@ struct Problem {
   int n, nnz, p;
   const int* rp;
   const int* ci;
-  const double* val;
-  float* val32;             // filled by the setup phase when T = float
+  const void* val;          // CSR values, of the kernel's value type VT (float64 or float32)
   const double* b;          // n x (p+1), leading dimension ldb
   long long ldb;
   double* u;
@@ -52,6 +50,8 @@ struct Problem {
   double tau_fixed;
   long long max_attempts;
   int symm, m_init, m_max, adapt_m, corrector, validate;
+  int full_reorth;          // Lanczos: orthogonalise against every basis vector
+  int fp32_flags;           // PHIPM_FP32_* bits (FP32 basis only)
   const float* proposer;    // MLP parameters, or null
   double* history;          // {tau, m, omega, valid} carried across calls, or null
   struct TraceStep* trace;  // per accepted step records, or null
@@ -80,19 +80,22 @@ struct Stats {              // mirrors phipm_stats
   double rho_max;
   long long prec_rejects;
   double fp32_err;          // accumulated FP32 rounding estimate (absolute)
-  int fp64_fallback, trace_len;
+  int fp64_steps, trace_len;
   long long proposals;      // steps seeded by the proposer
+  double bytes_ref;         // the same passes priced by the plain CGS2 byte model
 };
 
 struct State {
   double t_end, sgn, anorm, bnorm, bd_tol;
   double t, tau, beta;
   double bytes;             // algorithmic HBM bytes so far
+  double bytes_ref;         // bytes of the plain CGS2 model (reference byte count)
   double unorm;             // ||u_k||_2 of the current state
   double rho_max;           // largest ||beta y|| / ||u_k|| seen (FP32 basis)
-  long long prec_rejects;   // attempts rejected for FP32 rounding
-  double fp32_err;          // sum over accepted steps of the FP32 rounding estimate
-  int need_fp64, pad3;      // the FP32 estimate ran over budget: solve again in FP64
+  long long prec_rejects;   // FP32 attempts repeated with the FP64 basis
+  double fp32_err;          // sum over accepted FP32 steps of the rounding estimate
+  int redo64;               // the last attempt is to be repeated with the FP64 basis
+  int steps64;              // accepted steps built with the FP64 basis (FP32 mode)
   // step history (proposer features, warm start, trace)
   float feat[MLP_IN];       // features at the start of the current step
   double tau_prev, omega_prev, tau_prop;
@@ -157,9 +160,24 @@ __device__ __forceinline__ void add_matvec(State* st, double bytes) {
 }
 __device__ __forceinline__ void add_bytes(State* st, double bytes) { atomicAdd(&st->bytes, bytes); }
 
-// Algorithmic HBM bytes of one CSR product y = A x with value/vector width s.
-__device__ __forceinline__ double spmv_bytes(const Problem& P, double s) {
-  return (s + 4.0) * P.nnz + 4.0 * (P.n + 1.0) + 2.0 * s * P.n;
+// Algorithmic HBM bytes of one CSR product y = A x with values of sv bytes
+// and vectors of s bytes.
+__device__ __forceinline__ double spmv_bytes(const Problem& P, double sv, double s) {
+  return (sv + 4.0) * P.nnz + 4.0 * (P.n + 1.0) + 2.0 * s * P.n;
+}
+
+// Reference byte model of one Krylov step that builds basis vector j + 1
+// (0-based j) with plain CGS2, whatever this solver's fused passes stream:
+// the product plus two Gram-Schmidt passes that each read the j + 1 basis
+// vectors twice, plus the traffic of w and the normalisation, (4 (j + 1) + 8)
+// vectors (Arnoldi); a Lanczos step streams 16 vectors.
+// For the `cnt` products j = j0 .. j0 + cnt - 1 of one build:
+__device__ __forceinline__ double krylov_ref_bytes(const Problem& P, double sv, double s, int j0,
+                                                   int cnt, bool lanczos) {
+  // sum over j of 4 (j + 1) + 8 = 4 (cnt (j0 + 1) + cnt (cnt - 1) / 2) + 8 cnt
+  const double c = cnt;
+  const double vecs = lanczos ? 16.0 * c : 4.0 * (c * (j0 + 1.0) + 0.5 * c * (c - 1.0)) + 8.0 * c;
+  return c * spmv_bytes(P, sv, s) + vecs * s * P.n;
 }
 
 // Rows owned by this workgroup.  When the team size is a multiple of 8 the
@@ -326,6 +344,7 @@ __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, i
 // coefficients until finalised.
 struct KrylovCtl {
   int have, u_final, broke, final_col;  // final_col: H column have-1 is final
+  int products;                         // products with A made by this build
 };
 
 // Second pass of the candidate in U against columns [zb, j) of V and its
@@ -381,9 +400,9 @@ __device__ __forceinline__ double second_pass(const Team& tm, const Work<T>& w, 
 // most recent ones (second pass of u_j over {j-2, j-1}, first pass of A v_j
 // over {j-1, j}).  With seed != null (j = 0) v_0 = seed * seed_scale is
 // gathered directly and stored.  Returns false if the team was aborted.
-template <typename T, typename S>
+template <typename T, typename VT, typename S>
 __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, const Work<T>& w,
-                                            const T* valT, double sgn, bool lanczos, double bd_tol,
+                                            const VT* valT, double sgn, bool lanczos, double bd_tol,
                                             KrylovCtl& kc, const S* seed, double seed_scale,
                                             int rb, int re, Shared& sh) {
   const int j = kc.have;
@@ -398,10 +417,10 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
       double acc;
       if (seed) {
         auto ld = [&](int c) -> double { return (double)T(seed[c] * seed_scale); };
-        acc = spmv_tile<T, double>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), ld);
+        acc = spmv_tile<VT, double>(P.rp, P.ci, valT, r0, r1, smem_for<VT>(sh), ld);
       } else {
         auto ld = [&](int c) -> double { return (double)U[c]; };
-        acc = spmv_tile<T, double, 8>(P.rp, P.ci, valT, r0, r1, smem_for<T>(sh), ld);
+        acc = spmv_tile<VT, double, 8>(P.rp, P.ci, valT, r0, r1, smem_for<VT>(sh), ld);
       }
       const int r = r0 + threadIdx.x;
       if (r < r1) {
@@ -438,12 +457,13 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
     if (threadIdx.x == 0) {
       w.Hm[(long long)j * M_CAP + (j - 1)] = beta;
       if (tm.rank == 0) {
-        add_matvec(w.st, spmv_bytes(P, sizeof(T)) + (K + 2.0) * sizeof(T) * (double)P.n);
+        add_matvec(w.st, spmv_bytes(P, sizeof(VT), sizeof(T)) + (K + 2.0) * sizeof(T) * (double)P.n);
       }
     }
     __syncthreads();
     kc.broke = 1;
     kc.final_col = 1;
+    kc.products += 1;
     return true;
   }
   // g = H s over rows [ub, j) from the stored H (its column j-1 still holds
@@ -504,7 +524,7 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
     if (tm.rank == 0) {
       // product (+ the v_0 store), the fused dots (K columns, u, w), the
       // row-local pass (KU columns, u, w read; v_j, u written)
-      add_matvec(w.st, spmv_bytes(P, sizeof(T)) + (seed ? 2.0 : 0.0) * sizeof(T) * (double)P.n +
+      add_matvec(w.st, spmv_bytes(P, sizeof(VT), sizeof(T)) + (seed ? 2.0 : 0.0) * sizeof(T) * (double)P.n +
                            (K + 2.0 + KU + 2.0 + (uf ? 1.0 : 2.0)) * sizeof(T) * (double)P.n);
     }
   }
@@ -537,6 +557,7 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
   kc.have = j + 1;
   kc.u_final = 0;
   kc.final_col = 0;
+  kc.products += 1;
   return true;
 }
 
@@ -589,21 +610,28 @@ __device__ __forceinline__ bool krylov_finalize(const Team& tm, const Problem& P
   return true;
 }
 
-enum { SOLVE_DONE = 0, SOLVE_ABORTED = -1, SOLVE_NEEDS_FP64 = 1 };
+enum { SOLVE_DONE = 0, SOLVE_ABORTED = -1 };
 
-// Share of the tolerance the FP32 rounding estimate may take (absolute,
-// against max(1, ||u_k||) after every accepted step).
-constexpr double FP32_BUDGET = 2.0;
+// Share of the tolerance the FP32 rounding estimates of a solve may take
+// together (absolute, against max(1, ||u_k||)).
+constexpr double FP32_BUDGET = 1.0;
 
 // Scalars the decision step needs (passed by value so that the out-of-line
 // call does not force the kernel arguments into private memory).
 struct DecideArgs {
   double tol, tau_fixed, nnz, n;
   long long max_attempts;
-  int p, adapt_m, corrector, have, broke, fp32;
+  int p, adapt_m, corrector, have, broke;
+  int fp32;        // this attempt's basis is FP32
+  int fp32mode;    // the solve runs in FP32-basis mode (some steps may use FP64)
   TraceStep* trace;
-  int trace_cap, pad;
+  int trace_cap;
+  int fp32_flags;  // PHIPM_FP32_* bits
+  int window;      // windowed Lanczos: the eq. 4 cost of Lanczos (else Arnoldi's)
 };
+
+// FP32-basis option bits (phipm_opts.fp32_flags).
+enum { FP32_ONLY = 1 };
 
 // Unit roundoff of the FP32 basis.
 constexpr double EPS32 = 5.9604644775390625e-08;
@@ -647,6 +675,7 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
     eps = beta * fabs(hnext) * fabs(c);
   }
   if (threadIdx.x == 0) {
+    const Alg4Mem mem0 = st->mem;  // restored when the attempt is repeated in FP64
     if (beta > 0.0) st->expms += 1;
     st->attempts += 1;
     const double t = st->t, t_end = st->t_end;
@@ -667,7 +696,7 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       const double M = ctrl_M(knorm);
       const double rem = t_end - t;
       const double m_cost = m_new < 1.0 ? 1.0 : m_new;
-      const bool lz = st->lanczos != 0;
+      const bool lz = a.window != 0;
       const double c_tau = ctrl_C(rem, tau_new, ctrl_C1(lz, m_use, p, a.nnz, a.n, M));
       const double c_m = ctrl_C(rem, tau, ctrl_C1(lz, m_cost, p, a.nnz, a.n, M));
       accept = omega <= CTRL_DELTA;
@@ -698,52 +727,32 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       mem.m = m_use;
       mem.rejected = !accept;
     }
-    // FP32 basis: the phi-part beta*V*y is added to the Taylor part of eq. step
-    // and may be rho = ||beta y|| / ||u_k|| times larger than the result.  Its
-    // FP32 error is about EPS32 * rho * max(1, ||tau K||_1): the basis and the
-    // entries of H carry FP32 rounding, and the exponential amplifies a
-    // relative change of tau H by up to ||tau H||.  That must fit the step's
-    // share of the relative budget, 5 tol sqrt(tau / t_end).  When the
-    // phi-part dominates (rho > 4) and the rounding does not fit, the attempt
-    // is rejected and tau shrunk (the Krylov basis does not depend on tau); on
-    // acceptance the same bound caps the next tau.  With rho = O(1) FP32 is at
-    // its floor and a smaller tau would not help.
-    double fp32_est = 0.0;  // absolute FP32 rounding estimate of this step's phi-part
-    if (a.fp32 && beta > 0.0) {
-      double ys = 0.0;
-      for (int k = 0; k < m_use; ++k) ys += st->yb[k] * st->yb[k];
-      fp32_est = EPS32 * sqrt(ys) * (knorm > 1.0 ? knorm : 1.0);
-    }
-    if (a.fp32 && beta > 0.0 && !(a.tau_fixed > 0.0) && isfinite(omega)) {
+    // FP32 basis.  The phi-part beta V y of eq. step carries the rounding of
+    // the FP32 basis: to first order the basis is the exact Krylov basis of a
+    // matrix within relative EPS32 of A, which perturbs the phi-part by about
+    // EPS32 ||beta y|| (on the benchmark operators the error of a whole FP32
+    // solve against the oracle is 0.1 to 1 times the sum of these estimates).
+    // The estimates of the FP32 steps are summed; an attempt whose estimate
+    // would take the sum past FP32_BUDGET tol max(1, ||u_k||) is repeated with
+    // the FP64 basis at the same tau and m (the error estimate accepted it, so
+    // this is not a rejection of Algorithm 3).
+    double fp32_est = 0.0;
+    if (a.fp32mode && beta > 0.0) {
       double ys = 0.0;
       for (int k = 0; k < m_use; ++k) ys += st->yb[k] * st->yb[k];
       const double rho = sqrt(ys) / (st->unorm > 0.0 ? st->unorm : 1.0);
       if (rho > st->rho_max) st->rho_max = rho;
-      if (rho > 4.0) {
-        const double est = EPS32 * rho * (knorm > 1.0 ? knorm : 1.0);
-        const double allow = 5.0 * a.tol * sqrt(tau / t_end);
-        const double f = pow(allow / est, 1.0 / (double)(p + 1));
-        double tcap = tau * (f < 0.2 ? 0.2 : 0.9 * f);
-        if (est > allow && accept) {
-          accept = 0;
-          st->prec_rejects += 1;
-          tau_next = tcap < tau_next ? tcap : tau_next;
-          m_next = m_use;
-          mem.rejected = 1;
-          mem.branch = 1;
-        } else if (tcap < tau_next) {
-          tau_next = tcap;
-        }
-      }
+      if (a.fp32) fp32_est = EPS32 * sqrt(ys);
     }
-    // FP32 basis: the absolute rounding estimate accumulated over the accepted
-    // steps must stay within FP32_BUDGET tol max(1, ||u_k||); an attempt that
-    // would take it over ends the FP32 solve (the caller repeats it in FP64).
-    if (a.fp32 && accept && !(a.tau_fixed > 0.0) &&
+    st->redo64 = 0;
+    if (a.fp32 && accept && !(a.fp32_flags & FP32_ONLY) && !(a.tau_fixed > 0.0) &&
         st->fp32_err + fp32_est > FP32_BUDGET * a.tol * fmax(1.0, st->unorm)) {
       accept = 0;
-      st->need_fp64 = 1;
-      st->done = 1;
+      st->redo64 = 1;
+      st->prec_rejects += 1;
+      tau_next = tau;
+      m_next = m_use;
+      mem = mem0;
     }
     st->eps = eps;
     st->omega = omega;
@@ -789,12 +798,16 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       st->t = tn;
       st->steps += 1;
       st->fp32_err += fp32_est;
+      if (a.fp32mode && !a.fp32) st->steps64 += 1;
       st->tau_last = tau;
       st->m_last = m_use;
       st->mem = Alg4Mem{};
       st->done = tn >= t_end;
       st->m = m_next;
       st->tau = tau_next < t_end - tn ? tau_next : t_end - tn;
+    } else if (st->redo64) {
+      st->tau = tau_next;
+      st->m = m_next;
     } else {
       st->rejected += 1;
       st->step_rejects += 1;
@@ -874,21 +887,94 @@ __device__ __noinline__ void step_start(const float* proposer, double tol, int p
   __syncthreads();
 }
 
-// Solve one problem.  Returns SOLVE_DONE, SOLVE_ABORTED (a team wait ran out
-// of time; the team must stop) or, for the FP32 basis only, SOLVE_NEEDS_FP64:
-// the accumulated rounding estimate of the FP32 phi-parts exceeds
-// FP32_BUDGET tol max(1, ||u_k||), so the result could miss the tolerance and
-// the caller solves the problem again with the FP64 basis.  The return value
-// is the same in every workgroup of the team.
-template <typename T>
+// Build (or extend) the Krylov basis of w_p with basis type TB to `target`
+// columns and finalise the last one.  Returns false if the team was aborted.
+template <typename TB, typename VT>
+__device__ __forceinline__ bool build_basis(const Team& tm, const Problem& P, const Work<TB>& w,
+                                            const VT* val, double sgn, bool lanczos,
+                                            double bd_tol, KrylovCtl& kc, int target,
+                                            const double* wp, double beta, int rb, int re,
+                                            Shared& sh) {
+  const int j0 = kc.have;
+  kc.products = 0;
+  while (!kc.broke && kc.have < target && kc.have < P.n) {
+    const bool ok =
+        kc.have == 0
+            ? krylov_iter<TB, VT, double>(tm, P, w, val, sgn, lanczos, bd_tol, kc, wp, 1.0 / beta,
+                                          rb, re, sh)
+            : krylov_iter<TB, VT, double>(tm, P, w, val, sgn, lanczos, bd_tol, kc, nullptr, 0.0,
+                                          rb, re, sh);
+    if (!ok) return false;
+  }
+  if (!krylov_finalize<TB>(tm, P, w, lanczos, bd_tol, kc, rb, re, sh)) return false;
+  if (kc.have >= P.n) kc.broke = 1;  // the whole space: exact for any tau
+  if (tm.rank == 0 && threadIdx.x == 0 && kc.products > 0)
+    w.st->bytes_ref += krylov_ref_bytes(P, sizeof(VT), sizeof(TB), j0, kc.products, lanczos);
+  return true;
+}
+
+// The FP64 build of a step inside the FP32-basis solver, out of line: the
+// FP32 steps' inlined loop keeps its own register allocation.
+template <typename VT>
+__device__ __noinline__ bool build_basis64(const Team& tm, const Problem& P,
+                                           const Work<double>& w, const VT* val, double sgn,
+                                           bool lanczos, double bd_tol, KrylovCtl& kc, int target,
+                                           const double* wp, double beta, int rb, int re,
+                                           Shared& sh) {
+  return build_basis<double, VT>(tm, P, w, val, sgn, lanczos, bd_tol, kc, target, wp, beta, rb,
+                                 re, sh);
+}
+
+// eq. step with the corrected projection eq. phipapprox2 over the own rows:
+// u = sum_{j<p} tau^j/j! w_j + sum_k (beta y)_k v_k (+ the corrector term).
+// Coefficients in sh.coef / sh.yb.  Returns this thread's part of ||u||^2.
+template <typename TB>
+__device__ __forceinline__ double step_update(const Problem& P, const Work<TB>& w, int p, int mu,
+                                              bool use_v, bool use_corr, int rb, int re,
+                                              Shared& sh) {
+  double un = 0.0;
+  for (int r = rb + (int)threadIdx.x; r < re; r += BLOCK) {
+    double s = p > 0 ? sh.coef[0] * P.u[r] : 0.0;
+    for (int j = 1; j < p; ++j) s += sh.coef[j] * w.W[(long long)(j - 1) * w.ldw + r];
+    if (use_v) {
+      for (int k = 0; k < mu; ++k) s += sh.yb[k] * (double)w.V[(long long)k * w.ldv + r];
+      if (use_corr) s += sh.yb[mu] * (double)w.V[(long long)mu * w.ldv + r];
+    }
+    P.u[r] = s;
+    un += s * s;
+  }
+  return un;
+}
+
+__device__ __noinline__ double step_update64(const Problem& P, const Work<double>& w, int p,
+                                             int mu, bool use_v, bool use_corr, int rb, int re,
+                                             Shared& sh) {
+  return step_update<double>(P, w, p, mu, use_v, use_corr, rb, re, sh);
+}
+
+// Solve one problem.  Returns SOLVE_DONE, or SOLVE_ABORTED if a team wait ran
+// out of time (the team must stop); the same in every workgroup of the team.
+//
+// With T = float (FP32-basis mode) each step chooses its basis type before
+// its first attempt: FP32 unless the a-priori bound of its phi-part,
+// ||tau^p phi_p(tau A) w_p|| <= beta tau^p / p! (A dissipative), could take
+// the summed FP32 rounding estimates past their budget; then FP64 in the
+// same buffers (sized for FP64).  decide() checks the actual estimate of
+// every FP32 attempt and has it repeated in FP64 when it does not fit.
+template <typename T, typename VT>
 __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Work<T>& w, Shared& sh) {
   State* st = w.st;
   const int tid = threadIdx.x;
   const int n = P.n, p = P.p;
   int rb, re;
   own_rows(tm, n, rb, re);
-  const bool fp32 = sizeof(T) == 4;
-  bool fallback = false;
+  constexpr bool fp32 = sizeof(T) == 4;
+  const VT* val = static_cast<const VT*>(P.val);
+  // the same buffers seen with an FP64 basis (steps that need it)
+  const Work<double> w64{w.W, w.ldw, reinterpret_cast<double*>(w.V), w.ldv,
+                         reinterpret_cast<double*>(w.y0), reinterpret_cast<double*>(w.y1), w.H,
+                         w.ex, w.st, w.stats, w.Hm};
+  double unorm = 0.0;  // ||u_k||_2, identical in every workgroup
 
   // ---------------------------------------------------------------- setup
   {
@@ -910,7 +996,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       // after early exits from nested divergent loops)
       for (int k = k0; k < k1 && row_ok; ++k) {
         const int c = P.ci[k];
-        const double a = P.val[k];
+        const double a = (double)val[k];
         if (P.validate && (c < 0 || c >= n || c <= prev)) {
           f[0] = 1.0;
           row_ok = false;
@@ -920,7 +1006,6 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
           cmax = c > cmax ? c : cmax;
           if (!isfinite(a)) f[1] = 1.0;
           s += fabs(a);
-          if (fp32) P.val32[k] = (float)a;
           if (check_sym) {
             // binary search of row c for column r
             const int q0 = P.rp[c], q1 = P.rp[c + 1];
@@ -935,7 +1020,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
                 else { pos = mid; lo = hi + 1; }
               }
             }
-            const bool mirrored = pos >= 0 && P.val[pos] == a;
+            const bool mirrored = pos >= 0 && (double)val[pos] == a;
             f[2] = mirrored ? f[2] : 1.0;
           }
         }
@@ -1024,10 +1109,12 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       st->rho_max = 0.0;
       st->prec_rejects = 0;
       st->fp32_err = 0.0;
-      st->need_fp64 = 0;
+      st->redo64 = 0;
+      st->steps64 = 0;
       st->unorm = 0.0;
-      st->bytes = (check_sym ? 24.0 : 12.0) * P.nnz + 4.0 * (n + 1.0) + 8.0 * n * (p + 1.0) +
-                  (fp32 ? 4.0 * P.nnz : 0.0);
+      st->bytes = (check_sym ? 2.0 : 1.0) * (sizeof(VT) + 4.0) * P.nnz + 4.0 * (n + 1.0) +
+                  8.0 * n * (p + 1.0);
+      st->bytes_ref = 0.0;
     }
     if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
   }
@@ -1059,13 +1146,14 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
     if (tm.rank == 0 && tid == 0) st->bytes += 16.0 * n;
     block_reduce<1>(a1, RED_SUM, sh.blk);
     if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
-    if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
+    unorm = sqrt(sh.red[0]);
+    if (tm.rank == 0 && tid == 0) st->unorm = unorm;
   }
 
   {
-    const T* valT;
-    if constexpr (sizeof(T) == 4) valT = P.val32; else valT = P.val;
-    const bool lanczos = st->lanczos != 0;
+    // Lanczos orthogonalises against the two previous vectors, or (full
+    // reorthogonalisation) against all of them like Arnoldi
+    const bool lanczos = st->lanczos != 0 && !P.full_reorth;
     while (!st->done) {
       const double t = st->t;
       // ---- eq. wrecurrence: w_j = A w_{j-1} + sum_l t^l/l! b_{j+l} (A, b scaled by sgn)
@@ -1076,7 +1164,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         auto ld = [&](int c) -> double { return wprev[c]; };
         for (int r0 = rb; r0 < re; r0 += BLOCK) {
           const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
-          double acc = spmv_tile<double, double>(P.rp, P.ci, P.val, r0, r1, sh.sm64, ld);
+          double acc = spmv_tile<VT, double>(P.rp, P.ci, val, r0, r1, smem_for<VT>(sh), ld);
           const int r = r0 + tid;
           if (r < r1) {
             double s = sgn * acc;
@@ -1089,7 +1177,10 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
             nrm += s * s;
           }
         }
-        if (tm.rank == 0 && tid == 0) st->bytes += spmv_bytes(P, 8.0) + 8.0 * n * (p - j + 1.0);
+        if (tm.rank == 0 && tid == 0) {
+          st->bytes += spmv_bytes(P, sizeof(VT), 8.0) + 8.0 * n * (p - j + 1.0);
+          st->bytes_ref += spmv_bytes(P, sizeof(VT), 8.0) + 3.0 * 8.0 * n;  // w-recurrence
+        }
         if (j == p) {
           double a1[1] = {nrm};
           block_reduce<1>(a1, RED_SUM, sh.blk);
@@ -1120,38 +1211,64 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       }
       const double* wp = p == 0 ? P.u : w.W + (long long)(p - 1) * w.ldw;
 
-      // ---- attempts of this step (Algorithm 3 inner loop)
-      KrylovCtl kc{0, 1, 0, 1};  // v_0 = w_p / beta is final by construction
-      const double bd_tol = st->bd_tol;
-      // build (or extend) the basis to `target` columns and finalise the last
-      auto build = [&](int target) -> bool {
-        while (!kc.broke && kc.have < target && kc.have < n) {
-          const bool ok =
-              kc.have == 0
-                  ? krylov_iter<T, double>(tm, P, w, valT, sgn, lanczos, bd_tol, kc, wp, 1.0 / beta,
-                                           rb, re, sh)
-                  : krylov_iter<T, double>(tm, P, w, valT, sgn, lanczos, bd_tol, kc, nullptr, 0.0,
-                                           rb, re, sh);
-          if (!ok) return false;
+      // ---- basis type of this step (FP32-basis mode); team-uniform: every
+      // workgroup derives it from the same values
+      bool step64 = !fp32;
+      if constexpr (fp32) {
+        if (!(P.fp32_flags & FP32_ONLY) && !(P.tau_fixed > 0.0) && beta > 0.0) {
+          double bnd = beta;
+          const double tau0 = st->tau;
+          for (int j = 1; j <= p; ++j) bnd *= tau0 / (double)j;
+          step64 = st->fp32_err + EPS32 * bnd > FP32_BUDGET * P.tol * fmax(1.0, unorm);
         }
-        if (!krylov_finalize<T>(tm, P, w, lanczos, bd_tol, kc, rb, re, sh)) return false;
-        if (kc.have >= n) kc.broke = 1;  // the whole space: exact for any tau
-        return true;
+      }
+
+      // ---- attempts of this step (Algorithm 3 inner loop)
+      KrylovCtl kc{0, 1, 0, 1, 0};  // v_0 = w_p / beta is final by construction
+      const double bd_tol = st->bd_tol;
+      auto build = [&](int target) -> bool {
+        if constexpr (fp32) {
+          if (step64)
+            return build_basis64<VT>(tm, P, w64, val, sgn, lanczos, bd_tol, kc, target, wp, beta,
+                                     rb, re, sh);
+        }
+        return build_basis<T, VT>(tm, P, w, val, sgn, lanczos, bd_tol, kc, target, wp, beta, rb,
+                                  re, sh);
       };
+      int m = st->m;
       for (;;) {
-        const int m = st->m;
         if (beta > 0.0 && !build(m)) return SOLVE_ABORTED;
         const int have = kc.have;
         const bool broke = kc.broke != 0;
         if (tm.rank == 0) {
           DecideArgs da{P.tol, P.tau_fixed, (double)P.nnz, (double)n, P.max_attempts,
-                        p, P.adapt_m, P.corrector, have, broke ? 1 : 0, fp32 ? 1 : 0,
-                        P.trace, P.trace_cap, 0};
+                        p, P.adapt_m, P.corrector, have, broke ? 1 : 0,
+                        (fp32 && !step64) ? 1 : 0, fp32 ? 1 : 0,
+                        P.trace, P.trace_cap, P.fp32_flags, lanczos ? 1 : 0};
           decide(da, st, w.H, w.ex, sh.dense);
         }
-        if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
-        if (!st->accept) {
-          if (st->done) goto finish;  // attempt limit
+        // the decision reaches every workgroup with the synchronisation itself
+        // (sums of workgroup 0's values): state words that workgroup 0 may
+        // rewrite at its next attempt are never read after the barrier
+        if (tid < 4) {
+          double v = 0.0;
+          if (tm.rank == 0)
+            v = tid == 0 ? (double)st->accept
+                         : tid == 1 ? (double)st->done : tid == 2 ? (double)st->redo64 : (double)st->m;
+          sh.blk[tid] = v;
+        }
+        if (!team_sync(tm, sh.blk, 4, RED_SUM, sh.red)) return SOLVE_ABORTED;
+        const bool accept = sh.red[0] != 0.0;
+        const bool done = sh.red[1] != 0.0;
+        const bool redo64 = sh.red[2] != 0.0;
+        m = (int)sh.red[3];
+        if (!accept) {
+          if (done) goto finish;  // attempt limit
+          if (redo64) {
+            // this FP32 attempt's rounding did not fit: the step again in FP64
+            step64 = true;
+            kc = KrylovCtl{0, 1, 0, 1, 0};
+          }
           continue;
         }
         // ---- eq. step with the corrected projection eq. phipapprox2
@@ -1161,23 +1278,23 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         __syncthreads();
         const bool use_v = beta > 0.0;
         const bool use_corr = use_v && sh.yb[mu] != 0.0;
-        double un[1] = {0.0};
-        for (int r = rb + tid; r < re; r += BLOCK) {
-          double s = p > 0 ? sh.coef[0] * P.u[r] : 0.0;
-          for (int j = 1; j < p; ++j) s += sh.coef[j] * w.W[(long long)(j - 1) * w.ldw + r];
-          if (use_v) {
-            for (int k = 0; k < mu; ++k) s += sh.yb[k] * (double)w.V[(long long)k * w.ldv + r];
-            if (use_corr) s += sh.yb[mu] * (double)w.V[(long long)mu * w.ldv + r];
-          }
-          P.u[r] = s;
-          un[0] += s * s;
+        double un[1];
+        if constexpr (fp32) {
+          un[0] = step64 ? step_update64(P, w64, p, mu, use_v, use_corr, rb, re, sh)
+                         : step_update<T>(P, w, p, mu, use_v, use_corr, rb, re, sh);
+        } else {
+          un[0] = step_update<T>(P, w, p, mu, use_v, use_corr, rb, re, sh);
         }
-        if (tm.rank == 0 && tid == 0)
+        const double sv = step64 ? 8.0 : (double)sizeof(T);
+        if (tm.rank == 0 && tid == 0) {
           st->bytes += 8.0 * n * (p > 0 ? p + 1.0 : 1.0) +
-                       (use_v ? (mu + (use_corr ? 1.0 : 0.0)) * sizeof(T) * (double)n : 0.0);
+                       (use_v ? (mu + (use_corr ? 1.0 : 0.0)) * sv * (double)n : 0.0);
+          st->bytes_ref += (p + mu + 2.0) * sv * (double)n;
+        }
         block_reduce<1>(un, RED_SUM, sh.blk);
         if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
-        if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
+        unorm = sqrt(sh.red[0]);
+        if (tm.rank == 0 && tid == 0) st->unorm = unorm;
         if (P.trace && use_v) {
           // training record: extend the basis (prefix-stable, tau-independent)
           // to m_cap columns so that hindsight labels can weigh every m,
@@ -1197,13 +1314,6 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
             __syncthreads();
             if (tid == 0) st->trace_len = slot + 1;
           }
-        }
-        // st->fp32_err was written before the decision's team_sync, so every
-        // workgroup sees the same value and takes the same branch
-        if (fp32 && !(P.tau_fixed > 0.0) &&
-            st->fp32_err > FP32_BUDGET * P.tol * fmax(1.0, sqrt(sh.red[0]))) {
-          fallback = true;
-          goto finish;
         }
         break;
       }
@@ -1226,61 +1336,22 @@ finish:
     o->anorm = st->anorm;
     o->setup_flags = st->setup_flags;
     o->bytes = st->bytes;
+    o->bytes_ref = st->bytes_ref;
     o->rho_max = st->rho_max;
     o->prec_rejects = st->prec_rejects;
     o->fp32_err = st->fp32_err;
-    o->fp64_fallback = 0;
+    o->fp64_steps = st->steps64;
     o->trace_len = st->trace_len;
     o->proposals = st->proposals;
     // the next call's warm start: the proposal for the step after the last
-    if (P.history && st->status == ST_OK && st->steps > 0 && !fallback && !st->need_fp64) {
+    if (P.history && st->status == ST_OK && st->steps > 0) {
       P.history[0] = st->tau_prop;
       P.history[1] = (double)st->m_prop;
       P.history[2] = st->omega_prev;
       P.history[3] = 1.0;
     }
   }
-  return (fallback || st->need_fp64) ? SOLVE_NEEDS_FP64 : SOLVE_DONE;
-}
-
-// solve() with the FP32 basis, and again with the FP64 basis if the FP32
-// rounding estimate ran over its budget (the work buffer is sized for FP64
-// vectors in both cases).  The statistics of a fallback count the work of
-// both runs and carry the FP32 run's estimate.
-template <typename T>
-__device__ __forceinline__ int solve_mixed(const Team& tm, const Problem& P, const Work<T>& w,
-                                           Shared& sh) {
-  int r = solve<T>(tm, P, w, sh);
-  if constexpr (sizeof(T) == 4) {
-    if (r == SOLVE_NEEDS_FP64) {
-      __shared__ long long s_carry[4];
-      __shared__ double s_carry_d[2];
-      if (tm.rank == 0 && threadIdx.x == 0) {
-        const Stats* o = w.stats;
-        s_carry[0] = o->steps;
-        s_carry[1] = o->rejected;
-        s_carry[2] = o->matvecs;
-        s_carry[3] = o->expms;
-        s_carry_d[0] = o->bytes;
-        s_carry_d[1] = o->fp32_err;
-      }
-      Work<double> wd{w.W, w.ldw, reinterpret_cast<double*>(w.V), w.ldv,
-                      reinterpret_cast<double*>(w.y0), reinterpret_cast<double*>(w.y1), w.H,
-                      w.ex, w.st, w.stats, w.Hm};
-      r = solve<double>(tm, P, wd, sh);
-      if (r == SOLVE_DONE && tm.rank == 0 && threadIdx.x == 0) {
-        Stats* o = w.stats;
-        o->steps += s_carry[0];
-        o->rejected += s_carry[1];
-        o->matvecs += s_carry[2];
-        o->expms += s_carry[3];
-        o->bytes += s_carry_d[0];
-        o->fp32_err = s_carry_d[1];
-        o->fp64_fallback = 1;
-      }
-    }
-  }
-  return r;
+  return SOLVE_DONE;
 }
 
 }  // namespace pkr

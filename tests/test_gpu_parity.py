@@ -127,6 +127,31 @@ def test_krylov_matches_oracle(pk, lanczos):
     assert np.linalg.norm(AV - V @ H) <= 1e-12 * sp.linalg.norm(A) * math.sqrt(m)
 
 
+@pytest.mark.parametrize("case", ["convdiff-512 arnoldi m64", "laplace3d-128 lanczos m20"])
+def test_krylov_full_grid_matches_oracle(pk, case):
+    """The Krylov process on the full-size operators, where the library
+    spreads it over one workgroup per CU (256 workgroups: the multi-level team
+    reduction and the neighbour synchronisation), element by element against
+    the oracle's CGS2."""
+    say("krylov full grid", case)
+    if case.startswith("convdiff"):
+        A, m, lanczos = W.convdiff2d(512, 50.0, 50.0), 64, 0
+    else:
+        A, m, lanczos = W.laplace3d(128), 20, 1
+    n = A.shape[0]
+    v = np.random.default_rng(17).standard_normal(n)
+    V, H, done = pk.krylov(pk.DeviceCSR(A), dev(v), m, lanczos)
+    torch.cuda.synchronize()
+    V, H = V.cpu().numpy(), H.cpu().numpy()
+    Vr, Hr, _, mm = oracle.krylov(A, v, m, lanczos=bool(lanczos), reorth=1)
+    assert done == mm == m
+    eh = np.abs(H - Hr).max() / np.abs(Hr).max()
+    ev = np.abs(V - Vr).max() / np.abs(Vr).max()
+    say(f"  max |H - H_ref| / max |H_ref| = {eh:.2e}, max |V - V_ref| / max |V_ref| = {ev:.2e}")
+    assert eh <= 1e-10
+    assert ev <= 1e-8
+
+
 # ------------------------------------------------------------ solver level
 
 FIXED = [
@@ -185,7 +210,36 @@ def test_adaptive_matches_oracle(pk, name, build, p, t, tol):
     assert rel(u, ref) <= 10 * tol
     assert st["lanczos"] == int(oracle.is_symmetric(A))
     assert (st["setup_flags"] >> 2 & 1) == 1 - st["lanczos"]
+    # the same trajectory of Algorithm 3: every accept/reject decision and
+    # every change of tau and m agree with the oracle's
+    assert (st["steps"], st["rejected"], st["matvecs"], st["expms"]) == \
+        (ost["steps"], ost["rejected"], ost["matvecs"], ost["expms"])
     assert st["anorm"] == pytest.approx(abs(A).sum(axis=1).max(), rel=1e-14)
+
+
+@pytest.mark.parametrize("mode", ["fixed", "adaptive"])
+def test_full_reorth_lanczos_matches_oracle(pk, mode):
+    """Lanczos with CGS2 against every basis vector (Algorithm 2 with full
+    reorthogonalisation) against the oracle's same flavour."""
+    say("full-reorth lanczos", mode)
+    A = W.laplace3d(20)
+    b = np.random.default_rng(21).standard_normal((A.shape[0], 3))
+    if mode == "fixed":
+        kw = dict(tau_fixed=2e-4, m_init=40, m_max=40, adapt_m=0)
+        t, gate = 1e-3, 1e-11
+    else:
+        kw = dict(tol=1e-8)
+        t, gate = 4e-3, 10 * 1e-8
+    u, st = gpu_solve(pk, t, A, b, reorth=pk.REORTH_FULL, **kw)
+    ref, ost = oracle.phipm(t, A, b, reorth=2, **kw)
+    loc, lst = oracle.phipm(t, A, b, reorth=1, **kw)
+    say("  gpu", st, "\n  oracle", ost, "\n  rel", rel(u, ref))
+    assert st["status"] == 0 and st["lanczos"] == 1
+    assert rel(u, ref) <= gate
+    assert (st["steps"], st["rejected"], st["matvecs"], st["expms"]) == \
+        (ost["steps"], ost["rejected"], ost["matvecs"], ost["expms"])
+    # the windowed flavour is a different computation of the same result
+    assert rel(loc, ref) <= 10 * 1e-8 if mode == "adaptive" else True
 
 
 def brute_force(A, b, t):
@@ -360,31 +414,67 @@ def test_corner_coupling_matches_oracle(pk):
 
 
 FP32_CASES = [
-    # name, builder, p, t, tol
-    ("config1 lap2d-30 p1", None, 1, 1e-3, 1e-7),
-    ("lap3d-40 p3", lambda: W.laplace3d(40), 3, 1e-4, 1e-6),
-    ("convdiff-96 p0", lambda: W.convdiff2d(96, 40.0, 40.0), 0, 1e-2, 1e-7),
-    ("convdiff-96 p2", lambda: W.convdiff2d(96, 40.0, 40.0), 2, 1e-2, 1e-7),
-    ("reaction-128 p2", lambda: W.reaction2d(128, 5999), 2, 1e-3, 1e-6),
+    # name, builder, p, t, tol, expected basis use: "fp32" (every step FP32),
+    # "mixed" (some steps FP64), "fp64" (every step FP64)
+    ("config1 lap2d-30 p1", None, 1, 1e-3, 1e-7, "fp64"),
+    ("lap3d-40 p3", lambda: W.laplace3d(40), 3, 1e-4, 1e-6, "fp32"),
+    ("convdiff-96 p0", lambda: W.convdiff2d(96, 40.0, 40.0), 0, 1e-2, 1e-7, "mixed"),
+    ("convdiff-96 p2", lambda: W.convdiff2d(96, 40.0, 40.0), 2, 1e-2, 1e-7, "mixed"),
+    ("reaction-128 p2", lambda: W.reaction2d(128, 5999), 2, 1e-3, 1e-6, "fp64"),
+    ("lap2d-64 p1 smooth", None, 1, 2e-3, 1e-6, "fp32"),
 ]
 
 
-@pytest.mark.parametrize("name,build,p,t,tol", FP32_CASES)
-def test_fp32_basis_meets_gate(pk, name, build, p, t, tol):
-    """FP32 Krylov basis with FP64 Taylor part, exponential and control: within
-    10 tol (relative 2-norm) of the FP64 oracle."""
-    say("fp32 case", name)
-    if build is None:
+def fp32_problem(name, build, p):
+    if name.startswith("config1"):
         pb = W.config1()
-        A, b = pb.A, pb.b
-    else:
-        A = build()
-        b = np.random.default_rng(9).standard_normal((A.shape[0], p + 1))
+        return pb.A, pb.b
+    if name.startswith("lap2d-64 p1 smooth"):
+        # smooth data: the phi-part stays small, every step fits in FP32
+        A = W.laplace2d(64)
+        x = np.arange(1, 65) / 65.0
+        s = np.outer(np.sin(np.pi * x), np.sin(2 * np.pi * x)).ravel()
+        return A, np.stack([s, 0.5 * s], axis=1)
+    A = build()
+    return A, np.random.default_rng(9).standard_normal((A.shape[0], p + 1))
+
+
+@pytest.mark.parametrize("name,build,p,t,tol,use", FP32_CASES)
+def test_fp32_basis_meets_gate(pk, name, build, p, t, tol, use):
+    """FP32 Krylov basis with FP64 Taylor part, exponential and control: within
+    10 tol (relative 2-norm) of the FP64 oracle.  Each step picks its basis
+    type from the rounding budget; the cases cover solves that run wholly in
+    FP32, wholly in FP64 (the phi-part of eq. step far larger than u, as with
+    rough data and p >= 1) and mixed."""
+    say("fp32 case", name)
+    A, b = fp32_problem(name, build, p)
     u, st = gpu_solve(pk, t, A, b, tol=tol, precision=pk.FP32_BASIS)
-    ref, _ = oracle.phipm(t, A, b, tol=tol)
+    ref, ost = oracle.phipm(t, A, b, tol=tol)
     say("  gpu fp32", st, "rel", rel(u, ref))
     assert st["status"] == 0
     assert rel(u, ref) <= 10 * tol
+    if use == "fp32":
+        assert st["fp64_steps"] == 0 and st["steps"] >= 1
+    elif use == "fp64":
+        assert st["fp64_steps"] == st["steps"]
+    else:
+        assert 0 < st["fp64_steps"] < st["steps"]
+
+
+def test_fp32_only_diagnostic_shows_the_rounding(pk):
+    """With every step forced into FP32 (a diagnostic option) the rough-data
+    p = 2 solve leaves the gate: the per-step choice above is what keeps
+    FP32 results within it."""
+    say("fp32-only diagnostic")
+    A = W.convdiff2d(96, 40.0, 40.0)
+    b = np.random.default_rng(9).standard_normal((A.shape[0], 3))
+    ref, _ = oracle.phipm(1e-2, A, b, tol=1e-7)
+    u, st = gpu_solve(pk, 1e-2, A, b, tol=1e-7, precision=pk.FP32_BASIS,
+                      fp32_flags=pk.FP32_ONLY)
+    u2, st2 = gpu_solve(pk, 1e-2, A, b, tol=1e-7, precision=pk.FP32_BASIS)
+    say("  fp32-only rel", rel(u, ref), st, "\n  per-step rel", rel(u2, ref), st2)
+    assert st["status"] == 0 and st["fp64_steps"] == 0
+    assert rel(u, ref) > rel(u2, ref)
 
 
 @pytest.mark.parametrize("case", ["ragged-3000", "convdiff-64", "lap2d-40"])

@@ -169,6 +169,40 @@ def test_lanczos_tridiagonal(oracle_lib, reorth):
     assert np.allclose(H[:9, :8], H2, atol=1e-9 * np.abs(H2).max())
 
 
+def test_lanczos_full_reorth_keeps_orthogonality(oracle_lib):
+    # Algorithm 2 with classical Gram-Schmidt applied twice against every
+    # basis vector: orthonormal to rounding, and H tridiagonal up to rounding
+    # (symmetric A), over a run long enough for the three-term recurrence
+    # (and its local reorthogonalisation) to lose orthogonality: eigenvalues
+    # spread over six decades, the largest ones well separated
+    n = 1000
+    A = sp.diags(-np.logspace(0.0, 6.0, n)).tocsr()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int32)
+    v = np.random.default_rng(8).standard_normal(n)
+    m = 80
+    V, H, _, mm = oracle.krylov(A, v, m, lanczos=True, reorth=2)
+    assert mm == m
+    assert np.abs(V.T @ V - np.eye(m + 1)).max() < 1e-13
+    off = H - np.triu(np.tril(H, 1), -1)
+    assert np.abs(off).max() <= 1e-12 * np.abs(H).max()
+    for r in (0, 1):   # the recurrence alone, and with the two-vector window, drift
+        V0, _, _, _ = oracle.krylov(A, v, m, lanczos=True, reorth=r)
+        assert np.abs(V0.T @ V0 - np.eye(m + 1)).max() > 1e-3
+
+
+def test_lanczos_full_reorth_solve_is_the_arnoldi_solve(oracle_lib):
+    # full reorthogonalisation runs the Arnoldi process on the symmetric
+    # matrix and eq. 4 prices it as Arnoldi: the same solve, bit for bit
+    A = W.laplace2d(24)
+    b = np.random.default_rng(9).standard_normal((576, 3))
+    u1, s1 = oracle.phipm(4e-3, A, b, tol=1e-8, symm=1, reorth=2)
+    u2, s2 = oracle.phipm(4e-3, A, b, tol=1e-8, symm=0, reorth=1)
+    assert np.array_equal(u1, u2) and s1 == s2
+    u3, _ = oracle.phipm(4e-3, A, b, tol=1e-8, symm=1, reorth=1)
+    assert np.linalg.norm(u1 - u3) <= 10 * 1e-8 * np.linalg.norm(u3)
+
+
 # -------------------------------------------------------- controller pieces
 
 def test_tau0_matches_stirling_free_form(oracle_lib):
