@@ -178,10 +178,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs a) {
     P.validate = a.validate;
     P.full_reorth = a.full_reorth;
     P.fp32_flags = a.fp32_flags;
+    P.fp32mode = sizeof(T) == 4;
+    P.segment = SEG_WHOLE;
     P.proposer = a.proposer;
     w.stats = a.stats + id;
     if (rank == 0 && threadIdx.x == 0) a.clk[2 * id] = wall_clock64();
-    solve<T, VT>(tm, P, w, sh);
+    solve<T, VT, false>(tm, P, w, sh);
     if (rank == 0 && threadIdx.x == 0) a.clk[2 * id + 1] = wall_clock64();
   }
 }

@@ -15,10 +15,15 @@ namespace {
 
 // ------------------------------------------------------------ kernels
 
-__global__ void k_zero_ctl(TeamCtl* ctl, int count) {
+// Clears the team control block; keep_abort leaves the abort word as it is
+// (between the chained launches of one solve, so that a launch that timed out
+// stops the ones after it).
+__global__ void k_zero_ctl(TeamCtl* ctl, int count, int keep_abort) {
   unsigned* w = reinterpret_cast<unsigned*>(ctl);
   const size_t words = (size_t)count * sizeof(TeamCtl) / sizeof(unsigned);
-  for (size_t i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0u;
+  const size_t abort_word = offsetof(TeamCtl, abort) / sizeof(unsigned);
+  for (size_t i = threadIdx.x; i < words; i += blockDim.x)
+    if (!(keep_abort && i == abort_word)) w[i] = 0u;
 }
 
 // One 1024-thread workgroup per CU (16 waves, at most 128 VGPRs each).
@@ -32,7 +37,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve(Problem P, Work<T> w, TeamCtl* 
                             result, spin);
   Work<T> wk = w;
   wk.Hm = w.H + (size_t)blockIdx.x * H_WORDS;
-  solve<T, VT>(tm, P, wk, sh);
+  solve<T, VT, true>(tm, P, wk, sh);
 }
 
 // The solver kernel of a (basis, values) type pair: index 2 * fp32 basis +
@@ -254,8 +259,10 @@ int phipm_workspace_bytes(const phipm_csr* A, int p, const phipm_opts* o, size_t
   if (!csr_ok(A) || p < 0 || p > PHIPM_P_MAX || !opts_ok(o) || !bytes) return PHIPM_EINVAL;
   const DeviceInfo* d = device_info();
   if (!d) return PHIPM_EHIP;
-  const int kidx = 2 * (o->precision == PHIPM_FP32_BASIS) + (A->val_dtype == PHIPM_F32);
-  const int gmax = d->coresident[kidx];
+  const bool fp32 = o->precision == PHIPM_FP32_BASIS;
+  const int vf = A->val_dtype == PHIPM_F32;
+  const int kidx = 2 * fp32 + vf;
+  const int gmax = fp32 ? std::min(d->coresident[vf], d->coresident[kidx]) : d->coresident[kidx];
   const int m_cap = std::min(o->m_max, A->n);
   *bytes = layout(A->n, p, m_cap, gmax, choose_workgroups(o, A->n, gmax)).total;
   return PHIPM_OK;
@@ -271,8 +278,10 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   const DeviceInfo* d = device_info();
   if (!d) return fail(PHIPM_EHIP);
   const bool fp32 = o->precision == PHIPM_FP32_BASIS;
-  const int kidx = 2 * fp32 + (A->val_dtype == PHIPM_F32);
-  const int gmax = d->coresident[kidx];
+  const int vf = A->val_dtype == PHIPM_F32;
+  const int kidx = 2 * fp32 + vf;
+  // FP32 mode chains the FP64 and FP32 solvers: both must fit the grid
+  const int gmax = fp32 ? std::min(d->coresident[vf], d->coresident[kidx]) : d->coresident[kidx];
   const int m_cap = std::min(o->m_max, A->n);
   const int G = choose_workgroups(o, A->n, gmax);
   const Layout L = layout(A->n, p, m_cap, gmax, G);
@@ -305,6 +314,8 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   P.validate = o->validate;
   P.full_reorth = o->reorth == PHIPM_REORTH_FULL;
   P.fp32_flags = fp32 ? o->fp32_flags : 0;
+  P.fp32mode = fp32;
+  P.segment = SEG_WHOLE;
   P.proposer = o->proposer;
   P.history = o->history;
   P.trace = static_cast<TraceStep*>(o->trace);
@@ -316,13 +327,27 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   Stats* dstats = reinterpret_cast<Stats*>(ws + L.w.stats);
   unsigned long long spin = d->spin_ticks;
 
-  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1);
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1, 0);
   if (hipGetLastError() != hipSuccess) return fail(PHIPM_EHIP);
   hipError_t e;
   if (fp32) {
-    Work<float> w = work_at<float>(ws, L.w);
-    void* args[] = {&P, &w, &ctl, &part, &res, &spin};
-    e = hipLaunchCooperativeKernel(solve_kernel(kidx), dim3(G), dim3(BLOCK), args, 0, stream);
+    // FP64 steps from the start, FP32 steps, FP64 steps to the end
+    Work<double> w64 = work_at<double>(ws, L.w);
+    Work<float> w32 = work_at<float>(ws, L.w);
+    const int seg[3] = {SEG_LEAD, SEG_FP32, SEG_TAIL};
+    e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+      P.segment = seg[k];
+      if (k > 0) {
+        hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1, 1);
+        if (hipGetLastError() != hipSuccess) return fail(PHIPM_EHIP);
+      }
+      void* args64[] = {&P, &w64, &ctl, &part, &res, &spin};
+      void* args32[] = {&P, &w32, &ctl, &part, &res, &spin};
+      e = hipLaunchCooperativeKernel(solve_kernel(seg[k] == SEG_FP32 ? kidx : vf), dim3(G),
+                                     dim3(BLOCK), seg[k] == SEG_FP32 ? args32 : args64, 0,
+                                     stream);
+    }
   } else {
     Work<double> w = work_at<double>(ws, L.w);
     void* args[] = {&P, &w, &ctl, &part, &res, &spin};
@@ -438,7 +463,7 @@ int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double
   double* res = reinterpret_cast<double*>(ws + L.res);
   int* dm = reinterpret_cast<int*>(ws + L.w.stats);
   unsigned long long spin = d->spin_ticks;
-  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1);
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(1024), 0, stream, ctl, 1, 0);
   void* args[] = {&P, &w, &v, &m, &lanczos, &H, &dm, &ctl, &part, &res, &spin};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_krylov), dim3(G), dim3(BLOCK),
                                  args, 0, stream) != hipSuccess)

@@ -52,6 +52,8 @@ struct Problem {
   int symm, m_init, m_max, adapt_m, corrector, validate;
   int full_reorth;          // Lanczos: orthogonalise against every basis vector
   int fp32_flags;           // PHIPM_FP32_* bits (FP32 basis only)
+  int fp32mode;             // the solve runs in FP32-basis mode
+  int segment;              // SEG_*: which part of a chained FP32-basis solve this launch runs
   const float* proposer;    // MLP parameters, or null
   double* history;          // {tau, m, omega, valid} carried across calls, or null
   struct TraceStep* trace;  // per accepted step records, or null
@@ -95,7 +97,14 @@ struct State {
   long long prec_rejects;   // FP32 attempts repeated with the FP64 basis
   double fp32_err;          // sum over accepted FP32 steps of the rounding estimate
   int redo64;               // the last attempt is to be repeated with the FP64 basis
+  // the decision of attempt a in slot a % 2: {accept, done, redo64, m}.  A
+  // workgroup reads its slot after the decision's barrier; workgroup 0
+  // rewrites that slot only two attempts later, after a barrier that every
+  // workgroup reaches after reading it.
+  int dec[2][4];
   int steps64;              // accepted steps built with the FP64 basis (FP32 mode)
+  double tau_step0;         // tau and m at the start of the current step (before a
+  int m_step0, pad5;        // proposal), restored when a chained launch hands it on
   // step history (proposer features, warm start, trace)
   float feat[MLP_IN];       // features at the start of the current step
   double tau_prev, omega_prev, tau_prop;
@@ -633,6 +642,14 @@ struct DecideArgs {
 // FP32-basis option bits (phipm_opts.fp32_flags).
 enum { FP32_ONLY = 1 };
 
+// An FP32-basis solve runs as three chained launches on one stream: the
+// FP64 solver from the setup while its steps need FP64 (SEG_LEAD), the FP32
+// solver while they fit FP32 (SEG_FP32), the FP64 solver to the end
+// (SEG_TAIL).  Each kernel then holds only its own basis type's code.  A
+// launch that is not needed returns at once.  SEG_WHOLE: one launch does
+// everything (FP64 mode; the batched kernel).
+enum { SEG_WHOLE = 0, SEG_LEAD = 1, SEG_FP32 = 2, SEG_TAIL = 3 };
+
 // Unit roundoff of the FP32 basis.
 constexpr double EPS32 = 5.9604644775390625e-08;
 
@@ -819,6 +836,11 @@ __device__ __noinline__ void decide(DecideArgs a, State* st, const double* H, do
       st->done = 1;
       st->accept = 0;
     }
+    int* dec = st->dec[st->attempts & 1];
+    dec[0] = st->accept;
+    dec[1] = st->done;
+    dec[2] = st->redo64;
+    dec[3] = st->m;
   }
   __syncthreads();
 }
@@ -895,7 +917,6 @@ __device__ __forceinline__ bool build_basis(const Team& tm, const Problem& P, co
                                             double bd_tol, KrylovCtl& kc, int target,
                                             const double* wp, double beta, int rb, int re,
                                             Shared& sh) {
-  const int j0 = kc.have;
   kc.products = 0;
   while (!kc.broke && kc.have < target && kc.have < P.n) {
     const bool ok =
@@ -909,7 +930,8 @@ __device__ __forceinline__ bool build_basis(const Team& tm, const Problem& P, co
   if (!krylov_finalize<TB>(tm, P, w, lanczos, bd_tol, kc, rb, re, sh)) return false;
   if (kc.have >= P.n) kc.broke = 1;  // the whole space: exact for any tau
   if (tm.rank == 0 && threadIdx.x == 0 && kc.products > 0)
-    w.st->bytes_ref += krylov_ref_bytes(P, sizeof(VT), sizeof(TB), j0, kc.products, lanczos);
+    w.st->bytes_ref +=
+        krylov_ref_bytes(P, sizeof(VT), sizeof(TB), kc.have - kc.products, kc.products, lanczos);
   return true;
 }
 
@@ -961,7 +983,11 @@ __device__ __noinline__ double step_update64(const Problem& P, const Work<double
 // the summed FP32 rounding estimates past their budget; then FP64 in the
 // same buffers (sized for FP64).  decide() checks the actual estimate of
 // every FP32 attempt and has it repeated in FP64 when it does not fit.
-template <typename T, typename VT>
+// kChain: T = float runs only FP32 steps and hands the others on to the
+// chained FP64 launch (single solves); without it the FP32 solver builds
+// those steps with the FP64 basis itself (the batched kernel, whose teams
+// cannot relaunch).
+template <typename T, typename VT, bool kChain>
 __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Work<T>& w, Shared& sh) {
   State* st = w.st;
   const int tid = threadIdx.x;
@@ -974,10 +1000,36 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
   const Work<double> w64{w.W, w.ldw, reinterpret_cast<double*>(w.V), w.ldv,
                          reinterpret_cast<double*>(w.y0), reinterpret_cast<double*>(w.y1), w.H,
                          w.ex, w.st, w.stats, w.Hm};
-  double unorm = 0.0;  // ||u_k||_2, identical in every workgroup
+  const bool resume = P.segment == SEG_FP32 || P.segment == SEG_TAIL;
 
   // ---------------------------------------------------------------- setup
-  {
+  if (resume) {
+    // a chained launch: the state is in st; only the rows this workgroup's
+    // products read (the setup scan's column extent) are found again
+    int cmin = n, cmax = -1;
+    for (int r = rb + tid; r < re; r += BLOCK) {
+      const int k0 = P.rp[r], k1 = P.rp[r + 1];
+      if (k1 > k0) {
+        cmin = min(cmin, P.ci[k0]);
+        cmax = max(cmax, P.ci[k1 - 1]);
+      }
+    }
+    double cr[2] = {-(double)cmin, (double)cmax};
+    block_reduce<2>(cr, RED_MAX, sh.h1);
+    if (tid == 0) {
+      const long long chunk = row_chunk(n, tm.size);
+      const long long lo = (long long)(-sh.h1[0]), hi = (long long)sh.h1[1];
+      if (hi < lo || hi < 0) {
+        sh.dep_lo = 1;
+        sh.dep_hi = 0;
+      } else {
+        const long long slo = (lo < 0 ? 0 : lo) / chunk, shi = (hi >= n ? n - 1 : hi) / chunk;
+        sh.dep_lo = (int)slo;
+        sh.dep_hi = (int)(shi < tm.size - 1 ? shi : tm.size - 1);
+      }
+    }
+    __syncthreads();
+  } else {
     // structure / finiteness / symmetry flags and the row sums of |A|
     double f[4] = {0.0, 0.0, 0.0, 0.0};  // bad, nonfinite, asym, max row sum
     int cmin = n, cmax = -1;             // columns the own rows reference
@@ -1120,9 +1172,10 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
   }
   const double sgn = st->sgn;
   const double t_end = st->t_end;
-  if (st->status != ST_OK) goto finish;
+  long long natt = st->attempts;  // attempts decided so far (the decision slots' index)
+  if (st->status != ST_OK || st->done) goto finish;
 
-  if (st->zero_path) {
+  if (!resume && st->zero_path) {
     // A = 0, b = 0 or t = 0: u = sum_k t^k/k! b_k (phi_k(0) = 1/k!)
     for (int r = rb + tid; r < re; r += BLOCK) {
       double s = 0.0, f = 1.0;
@@ -1132,11 +1185,14 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       }
       P.u[r] = s;
     }
-    if (tm.rank == 0 && tid == 0) st->t = t_end;
+    if (tm.rank == 0 && tid == 0) {
+      st->t = t_end;
+      st->done = 1;
+    }
     goto finish;
   }
 
-  {
+  if (!resume) {
     double a1[1] = {0.0};
     for (int r = rb + tid; r < re; r += BLOCK) {
       const double v = P.b[r];
@@ -1146,8 +1202,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
     if (tm.rank == 0 && tid == 0) st->bytes += 16.0 * n;
     block_reduce<1>(a1, RED_SUM, sh.blk);
     if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
-    unorm = sqrt(sh.red[0]);
-    if (tm.rank == 0 && tid == 0) st->unorm = unorm;
+    if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
   }
 
   {
@@ -1204,6 +1259,30 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         if (!isfinite(beta)) { st->status = ST_ENONFINITE; }
       }
       if (!isfinite(beta)) goto finish;
+
+      // ---- basis type of this step (FP32-basis mode), from the plain
+      // controller's tau: FP32 unless the a-priori bound of the step's
+      // phi-part, ||tau^p phi_p(tau A) w_p|| <= beta tau^p / p! (A
+      // dissipative), could take the summed FP32 rounding estimates past
+      // their budget.  Team-uniform: every workgroup derives it from the
+      // same values.
+      bool step64 = !fp32;
+      if (P.fp32mode) {
+        bool need64 = false;
+        if (!(P.fp32_flags & FP32_ONLY) && !(P.tau_fixed > 0.0) && beta > 0.0) {
+          double bnd = beta;
+          const double tau0 = st->tau;
+          for (int j = 1; j <= p; ++j) bnd *= tau0 / (double)j;
+          need64 = st->fp32_err + EPS32 * bnd > FP32_BUDGET * P.tol * fmax(1.0, st->unorm);
+        }
+        // chained launches hand the step on at its start
+        if ((P.segment == SEG_LEAD && !need64) || (P.segment == SEG_FP32 && need64)) goto finish;
+        if constexpr (fp32 && !kChain) step64 = need64;
+      }
+      if (tm.rank == 0 && tid == 0) {
+        st->tau_step0 = st->tau;
+        st->m_step0 = st->m;
+      }
       // features of this step; the proposer (if any) seeds tau and m
       if (P.proposer || P.trace) {
         if (tm.rank == 0) step_start(P.proposer, P.tol, p, P.adapt_m, P.tau_fixed, st, beta);
@@ -1211,23 +1290,11 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       }
       const double* wp = p == 0 ? P.u : w.W + (long long)(p - 1) * w.ldw;
 
-      // ---- basis type of this step (FP32-basis mode); team-uniform: every
-      // workgroup derives it from the same values
-      bool step64 = !fp32;
-      if constexpr (fp32) {
-        if (!(P.fp32_flags & FP32_ONLY) && !(P.tau_fixed > 0.0) && beta > 0.0) {
-          double bnd = beta;
-          const double tau0 = st->tau;
-          for (int j = 1; j <= p; ++j) bnd *= tau0 / (double)j;
-          step64 = st->fp32_err + EPS32 * bnd > FP32_BUDGET * P.tol * fmax(1.0, unorm);
-        }
-      }
-
       // ---- attempts of this step (Algorithm 3 inner loop)
       KrylovCtl kc{0, 1, 0, 1, 0};  // v_0 = w_p / beta is final by construction
       const double bd_tol = st->bd_tol;
       auto build = [&](int target) -> bool {
-        if constexpr (fp32) {
+        if constexpr (fp32 && !kChain) {
           if (step64)
             return build_basis64<VT>(tm, P, w64, val, sgn, lanczos, bd_tol, kc, target, wp, beta,
                                      rb, re, sh);
@@ -1243,31 +1310,33 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         if (tm.rank == 0) {
           DecideArgs da{P.tol, P.tau_fixed, (double)P.nnz, (double)n, P.max_attempts,
                         p, P.adapt_m, P.corrector, have, broke ? 1 : 0,
-                        (fp32 && !step64) ? 1 : 0, fp32 ? 1 : 0,
+                        (fp32 && !step64) ? 1 : 0, P.fp32mode,
                         P.trace, P.trace_cap, P.fp32_flags, lanczos ? 1 : 0};
           decide(da, st, w.H, w.ex, sh.dense);
         }
-        // the decision reaches every workgroup with the synchronisation itself
-        // (sums of workgroup 0's values): state words that workgroup 0 may
-        // rewrite at its next attempt are never read after the barrier
-        if (tid < 4) {
-          double v = 0.0;
-          if (tm.rank == 0)
-            v = tid == 0 ? (double)st->accept
-                         : tid == 1 ? (double)st->done : tid == 2 ? (double)st->redo64 : (double)st->m;
-          sh.blk[tid] = v;
-        }
-        if (!team_sync(tm, sh.blk, 4, RED_SUM, sh.red)) return SOLVE_ABORTED;
-        const bool accept = sh.red[0] != 0.0;
-        const bool done = sh.red[1] != 0.0;
-        const bool redo64 = sh.red[2] != 0.0;
-        m = (int)sh.red[3];
+        if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
+        // this attempt's slot: workgroup 0 may already be deciding the next
+        // attempt (in the other slot) when a slow workgroup reads it
+        const volatile int* dec = st->dec[++natt & 1];
+        const bool accept = dec[0] != 0;
+        const bool done = dec[1] != 0;
+        const bool redo64 = dec[2] != 0;
+        m = dec[3];
         if (!accept) {
           if (done) goto finish;  // attempt limit
           if (redo64) {
             // this FP32 attempt's rounding did not fit: the step again in FP64
-            step64 = true;
-            kc = KrylovCtl{0, 1, 0, 1, 0};
+            if constexpr (kChain) {
+              // by the chained FP64 launch, from the step's start
+              if (tm.rank == 0 && tid == 0) {
+                st->tau = st->tau_step0;
+                st->m = st->m_step0;
+              }
+              goto finish;
+            } else {
+              step64 = true;
+              kc = KrylovCtl{0, 1, 0, 1, 0};
+            }
           }
           continue;
         }
@@ -1279,7 +1348,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         const bool use_v = beta > 0.0;
         const bool use_corr = use_v && sh.yb[mu] != 0.0;
         double un[1];
-        if constexpr (fp32) {
+        if constexpr (fp32 && !kChain) {
           un[0] = step64 ? step_update64(P, w64, p, mu, use_v, use_corr, rb, re, sh)
                          : step_update<T>(P, w, p, mu, use_v, use_corr, rb, re, sh);
         } else {
@@ -1293,8 +1362,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         }
         block_reduce<1>(un, RED_SUM, sh.blk);
         if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
-        unorm = sqrt(sh.red[0]);
-        if (tm.rank == 0 && tid == 0) st->unorm = unorm;
+        if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
         if (P.trace && use_v) {
           // training record: extend the basis (prefix-stable, tau-independent)
           // to m_cap columns so that hindsight labels can weigh every m,
@@ -1344,7 +1412,7 @@ finish:
     o->trace_len = st->trace_len;
     o->proposals = st->proposals;
     // the next call's warm start: the proposal for the step after the last
-    if (P.history && st->status == ST_OK && st->steps > 0) {
+    if (P.history && st->status == ST_OK && st->steps > 0 && st->done) {
       P.history[0] = st->tau_prop;
       P.history[1] = (double)st->m_prop;
       P.history[2] = st->omega_prev;
