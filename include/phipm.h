@@ -169,8 +169,13 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
  * (synchronises the stream the call used). */
 int phipm_last_status(void);
 
-/* y = A x, the CSR product used inside the solver (device pointers, float64).
- * Same validity rules as phipm(); asynchronous. */
+/* y = A x with the solver's CSR product: the products with A that the Krylov
+ * processes of Sect. 3.1 (Algorithms 1 and 2) and eq. wrecurrence are built
+ * from.  x, y: device, n float64 entries (y must not overlap x); A's values in
+ * either val_dtype, accumulated in float64.  Same validity rules as phipm()
+ * (an invalid CSR structure is not detected here: pass a valid matrix);
+ * asynchronous.  Returns PHIPM_OK, PHIPM_EINVAL for a null pointer or a bad
+ * descriptor, PHIPM_EHIP. */
 int phipm_spmv(const phipm_csr* A, const double* x, double* y, phipm_stream_t stream);
 
 /* Pointwise data of one exponential Rosenbrock-Euler step for the Allen-Cahn
@@ -198,9 +203,17 @@ int phipm_allen_cahn_update(const phipm_csr* L, double* u, const double* du,
 int phipm_expm(int N, const double* H, double* E, double* scratch, phipm_stream_t stream);
 
 /* m steps of the solver's Krylov process started from v (device, n entries):
- * V (device, n x (m+1) column-major, leading dimension n) and H (device,
- * (m+1) x m row-major), in float64 with the Arnoldi (lanczos = 0) or Lanczos
- * (lanczos = 1) flavour.  Returns the number of steps done in *m_done (host). */
+ * the Arnoldi process of Algorithm 1 (lanczos = 0) or the Lanczos process of
+ * Algorithm 2 (lanczos = 1), Sect. 3.1, each with classical Gram-Schmidt
+ * applied twice (Lanczos against the two previous vectors).  Outputs, in
+ * float64: V (device, n x (m+1) column-major, leading dimension n: the
+ * orthonormal basis v_1..v_{m+1} with v_1 = v / ||v||) and H (device,
+ * (m+1) x m row-major: the Hessenberg matrix with A V_m = V_{m+1} H).  The
+ * number of steps done (< m after a happy breakdown) goes to *m_done (host).
+ * A: float64 values only (PHIPM_EINVAL otherwise); 1 <= m <= PHIPM_M_CAP.
+ * workspace: device, 256-byte aligned, at least phipm_workspace_bytes() for
+ * p = 0 and m_max = max(m, 10).  Synchronises the stream.  Returns PHIPM_OK,
+ * PHIPM_EINVAL, PHIPM_ENOMEM (workspace too small), PHIPM_EHIP. */
 int phipm_krylov(const phipm_csr* A, const double* v, int m, int lanczos, double* V, double* H,
                  void* workspace, size_t ws_bytes, int* m_done, phipm_stream_t stream);
 

@@ -125,7 +125,7 @@ def sine_mode2d(N: int, k1: int, k2: int) -> tuple[np.ndarray, float]:
 def heston(Ns: int = 100, Nv: int = 51, K: float = 100.0, S: float = 800.0, V: float = 5.0,
            kappa: float = 2.0, eta: float = 0.2, lam: float = 0.3, rho: float = 0.8,
            rd: float = 0.03, rf: float = 0.0):
-    """Finite-difference Heston operator of the paper's Sect. 5.1: u' = A u + b1,
+    """Finite-difference Heston operator of the paper's Sect. 4.1: u' = A u + b1,
     u(0) = b0 (the call payoff).
 
     Grid: s_i = i ds (i = 1..Ns, ds = S/(Ns+1)) and v_j = j dv (j = 0..Nv-1,
