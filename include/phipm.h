@@ -42,7 +42,8 @@ enum {
   PHIPM_ENONFINITE = -4, /* NaN/Inf in A, b or t */
   PHIPM_EMAXSTEPS = -5,  /* attempt limit reached before t_end */
   PHIPM_EUNSUPPORTED = -6,
-  PHIPM_EABORT = -7      /* a device-side wait exceeded its time budget; results invalid */
+  PHIPM_EABORT = -7,     /* a device-side wait exceeded its time budget; results invalid */
+  PHIPM_ESCRATCH = -8    /* phipm_noalloc: the problem needs more than its fixed scratch */
 };
 
 enum { PHIPM_F64 = 0, PHIPM_F32 = 1 };
@@ -164,6 +165,26 @@ int phipm_workspace_bytes(const phipm_csr* A, int p, const phipm_opts* opts, siz
 int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts* opts,
           double* u, void* workspace, size_t ws_bytes, phipm_stats* stats,
           phipm_stream_t stream);
+
+/* phipm() without a caller workspace and without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The workspace is a fixed array of
+ * phipm_noalloc_scratch_bytes() (64 MiB) in the library's device code, one
+ * per GPU, held until the process ends; the call allocates nothing (no
+ * hipMalloc, no allocating library routine).  Arguments, results, status
+ * codes and synchronisation as for phipm(), plus PHIPM_ESCRATCH (checked on
+ * the host before any device work) when phipm_workspace_bytes() for this
+ * problem exceeds the fixed size: roughly n (m_max + 4) 8 bytes plus 132 KB
+ * per workgroup must fit, e.g. n = 65536 with the default options.  Every
+ * call on a GPU uses that GPU's one array: calls that overlap on one GPU
+ * (other host threads, other streams) race and must be serialised by the
+ * caller; a call leaves its data in the array, and the solver writes every
+ * word it reads before reading it. */
+int phipm_noalloc(double t, const phipm_csr* A, int p, const double* b, const phipm_opts* opts,
+                  double* u, phipm_stats* stats, phipm_stream_t stream);
+
+/* Size of phipm_noalloc()'s fixed device scratch, in bytes. */
+size_t phipm_noalloc_scratch_bytes(void);
 
 /* Status of the last phipm() on this host thread as seen on the device
  * (synchronises the stream the call used). */

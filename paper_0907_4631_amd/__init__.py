@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libphipm.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EMAXSTEPS, EUNSUPPORTED, EABORT = 0, -1, -2, -3, -4, -5, -6, -7
+ESCRATCH = -8
 FP64, FP32_BASIS = 0, 1
 F64, F32 = 0, 1                        # CSR value types (phipm_csr.val_dtype)
 REORTH_LOCAL, REORTH_FULL = 0, 1
@@ -108,7 +109,8 @@ EXPORTS = ["phipm_default_opts", "phipm_workspace_bytes", "phipm", "phipm_last_s
            "phipm_default_plan_opts", "phipm_plan_create", "phipm_plan_execute",
            "phipm_plan_stats", "phipm_plan_get_info", "phipm_plan_destroy", "phipm_batched",
            "phipm_batch_layout", "phipm_mlp_forward", "phipm_mlp_grad", "phipm_mlp_train",
-           "phipm_label_workspace_bytes", "phipm_label_steps", "phipm_allen_cahn_update"]
+           "phipm_label_workspace_bytes", "phipm_label_steps", "phipm_allen_cahn_update",
+           "phipm_noalloc", "phipm_noalloc_scratch_bytes"]
 
 
 def lib():
@@ -127,6 +129,11 @@ def lib():
         L.phipm.argtypes = [C.c_double, C.POINTER(CSR), C.c_int, vp, C.POINTER(Opts), vp, vp,
                             C.c_size_t, C.POINTER(Stats), vp]
         L.phipm.restype = C.c_int
+        L.phipm_noalloc.argtypes = [C.c_double, C.POINTER(CSR), C.c_int, vp, C.POINTER(Opts), vp,
+                                    C.POINTER(Stats), vp]
+        L.phipm_noalloc.restype = C.c_int
+        L.phipm_noalloc_scratch_bytes.argtypes = []
+        L.phipm_noalloc_scratch_bytes.restype = C.c_size_t
         L.phipm_last_status.argtypes = []
         L.phipm_last_status.restype = C.c_int
         L.phipm_spmv.argtypes = [C.POINTER(CSR), vp, vp, vp]
@@ -278,6 +285,22 @@ def solve(t, A: DeviceCSR, b, opts: Opts | None = None, **kw):
     u = torch.empty(A.n, dtype=torch.float64, device=b.device)
     st = s(t, b, u)
     return u, st
+
+
+def solve_noalloc(t, A: DeviceCSR, b, u, opts: Opts | None = None, stats: bool = True,
+                  stream=None, **kw):
+    """u <- sum_k t^k phi_k(tA) b_k with phipm_noalloc (the library's fixed
+    device scratch, no allocation).  b: (p+1, n) float64 tensor."""
+    torch = _torch()
+    assert b.dtype == torch.float64 and u.dtype == torch.float64 and b.is_contiguous()
+    o = opts if opts is not None else default_opts(**kw)
+    st = Stats()
+    rc = lib().phipm_noalloc(float(t), C.byref(A.c()), int(b.shape[0] - 1),
+                             C.c_void_p(b.data_ptr()), C.byref(o), C.c_void_p(u.data_ptr()),
+                             C.byref(st) if stats else None, _stream_ptr(stream))
+    if rc != OK:
+        raise PhipmError(rc, "phipm_noalloc")
+    return st.as_dict() if stats else None
 
 
 def spmv(A: DeviceCSR, x, y, stream=None):

@@ -209,6 +209,38 @@ Layout layout(int n, int p, int m_cap, int gmax, int groups) {
   return L;
 }
 
+// Device scratch of the allocation-free entry point phipm_noalloc(): a
+// file-scope array that every GPU the library runs on holds until the
+// process ends.  In host code its name is only a stand-in; the device
+// address of each GPU's copy comes from hipGetSymbolAddress (once per device,
+// kept in g_scratch) and only that address is passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+struct DeviceScratch {
+  void* ptr = nullptr;
+  bool ok = false;
+};
+DeviceScratch g_scratch[64];
+
+// This device's scratch address (null if it could not be obtained).
+void* device_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceScratch& s = g_scratch[dev];
+  if (!s.ok) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    s.ptr = ptr;
+    s.ok = true;
+  }
+  return s.ptr;
+}
+
 thread_local hipStream_t t_last_stream = nullptr;
 thread_local const Stats* t_last_stats = nullptr;
 thread_local const TeamCtl* t_last_ctl = nullptr;
@@ -372,6 +404,19 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
   return PHIPM_OK;
 }
 
+int phipm_noalloc(double t, const phipm_csr* A, int p, const double* b, const phipm_opts* o,
+                  double* u, phipm_stats* stats, phipm_stream_t stream) {
+  size_t need = 0;
+  const int rc = phipm_workspace_bytes(A, p, o, &need);
+  if (rc != PHIPM_OK) return fail(rc);
+  if (need > NOALLOC_SCRATCH_BYTES) return fail(PHIPM_ESCRATCH);
+  void* ws = device_scratch();
+  if (!ws) return fail(PHIPM_EHIP);
+  return phipm(t, A, p, b, o, u, ws, NOALLOC_SCRATCH_BYTES, stats, stream);
+}
+
+size_t phipm_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
 int phipm_last_status(void) {
   if (t_last_host_status != PHIPM_OK || !t_last_stats) return t_last_host_status;
   Stats hs;
@@ -484,6 +529,9 @@ const char* phipm_status_string(int s) {
     case PHIPM_EMAXSTEPS: return "attempt limit reached";
     case PHIPM_EUNSUPPORTED: return "unsupported";
     case PHIPM_EABORT: return "device wait exceeded its time budget";
+    case PHIPM_ESCRATCH:
+      return "problem needs more device scratch than phipm_noalloc holds "
+             "(phipm_noalloc_scratch_bytes()); use phipm() with a workspace";
     default: return "unknown status";
   }
 }
