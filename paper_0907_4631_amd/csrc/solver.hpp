@@ -959,8 +959,21 @@ __device__ __forceinline__ double step_update(const Problem& P, const Work<TB>& 
     double s = p > 0 ? sh.coef[0] * P.u[r] : 0.0;
     for (int j = 1; j < p; ++j) s += sh.coef[j] * w.W[(long long)(j - 1) * w.ldw + r];
     if (use_v) {
-      for (int k = 0; k < mu; ++k) s += sh.yb[k] * (double)w.V[(long long)k * w.ldv + r];
-      if (use_corr) s += sh.yb[mu] * (double)w.V[(long long)mu * w.ldv + r];
+      // four columns' loads issued together; the sum stays in column order
+      const TB* vp = w.V + r;
+      int k = 0;
+      for (; k + 4 <= mu; k += 4) {
+        const double v0 = (double)vp[(long long)k * w.ldv];
+        const double v1 = (double)vp[(long long)(k + 1) * w.ldv];
+        const double v2 = (double)vp[(long long)(k + 2) * w.ldv];
+        const double v3 = (double)vp[(long long)(k + 3) * w.ldv];
+        s += sh.yb[k] * v0;
+        s += sh.yb[k + 1] * v1;
+        s += sh.yb[k + 2] * v2;
+        s += sh.yb[k + 3] * v3;
+      }
+      for (; k < mu; ++k) s += sh.yb[k] * (double)vp[(long long)k * w.ldv];
+      if (use_corr) s += sh.yb[mu] * (double)vp[(long long)mu * w.ldv];
     }
     P.u[r] = s;
     un += s * s;
@@ -1058,22 +1071,49 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
           cmax = c > cmax ? c : cmax;
           if (!isfinite(a)) f[1] = 1.0;
           s += fabs(a);
-          if (check_sym) {
-            // binary search of row c for column r
-            const int q0 = P.rp[c], q1 = P.rp[c + 1];
-            int pos = -1;
-            if (q0 >= 0 && q1 <= P.nnz && q0 <= q1) {
-              int lo = q0, hi = q1 - 1;
-              while (lo <= hi) {
-                const int mid = (lo + hi) >> 1;
-                const int cm = P.ci[mid];
-                if (cm < r) lo = mid + 1;
-                else if (cm > r) hi = mid - 1;
-                else { pos = mid; lo = hi + 1; }
+        }
+      }
+      if (check_sym && row_ok) {
+        // a_rc == a_cr for every entry: binary searches of rows c for column
+        // r, eight entries of the row at a time in lock step, so that their
+        // loads are in flight together (the searches are latency-bound)
+        for (int kb = k0; kb < k1; kb += 8) {
+          int lo[8], hi[8], pos[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            lo[q] = 0;
+            hi[q] = -1;
+            pos[q] = -1;
+            if (kb + q < k1) {
+              const int c = P.ci[kb + q];
+              const int q0 = P.rp[c], q1 = P.rp[c + 1];
+              if (q0 >= 0 && q1 <= P.nnz && q0 <= q1) {
+                lo[q] = q0;
+                hi[q] = q1 - 1;
               }
             }
-            const bool mirrored = pos >= 0 && (double)val[pos] == a;
-            f[2] = mirrored ? f[2] : 1.0;
+          }
+          bool more = true;
+          while (more) {
+            more = false;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              if (lo[q] <= hi[q]) {
+                const int mid = (lo[q] + hi[q]) >> 1;
+                const int cm = P.ci[mid];
+                if (cm < r) lo[q] = mid + 1;
+                else if (cm > r) hi[q] = mid - 1;
+                else { pos[q] = mid; lo[q] = hi[q] + 1; }
+                more = more || lo[q] <= hi[q];
+              }
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (kb + q < k1) {
+              const bool mirrored = pos[q] >= 0 && (double)val[pos[q]] == (double)val[kb + q];
+              f[2] = mirrored ? f[2] : 1.0;
+            }
           }
         }
       }
@@ -1219,7 +1259,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         auto ld = [&](int c) -> double { return wprev[c]; };
         for (int r0 = rb; r0 < re; r0 += BLOCK) {
           const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
-          double acc = spmv_tile<VT, double>(P.rp, P.ci, val, r0, r1, smem_for<VT>(sh), ld);
+          double acc = spmv_tile<VT, double, 8>(P.rp, P.ci, val, r0, r1, smem_for<VT>(sh), ld);
           const int r = r0 + tid;
           if (r < r1) {
             double s = sgn * acc;
