@@ -40,6 +40,11 @@ MEASURED_TRAFFIC = {
 }
 
 
+def log(msg: str) -> None:
+    """Progress of a long run on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     """sha256[:16] of the kernel sources and the build script (its flags)."""
     import glob
@@ -171,6 +176,18 @@ def time_solves(solver, t, b, u, steps, warmup):
     return ev0.elapsed_time(ev1) / steps, st
 
 
+def fixed_m_kw(args):
+    """Solver options of the paper's phip (Krylov dimension fixed, only the
+    step size adapted) when --fixed-m is given; phipm's otherwise."""
+    if args.fixed_m > 0:
+        return dict(adapt_m=0, m_init=args.fixed_m, m_max=args.fixed_m)
+    return {}
+
+
+def method_name(args):
+    return f"phip (m fixed at {args.fixed_m})" if args.fixed_m > 0 else "phipm"
+
+
 def run_single(args, with_headline):
     import torch
     import paper_0907_4631_amd as pk
@@ -185,12 +202,12 @@ def run_single(args, with_headline):
     A = pk.DeviceCSR(pb.A, device="cuda", dtype=vdt)
     b = torch.as_tensor(np.ascontiguousarray(pb.b.T), device="cuda")
     u = torch.empty(pb.n, dtype=torch.float64, device="cuda")
-    kw = {}
-    if args.fixed_m > 0:
-        kw = dict(adapt_m=0, m_init=args.fixed_m, m_max=args.fixed_m)
+    kw = fixed_m_kw(args)
     solver = pk.Solver(A, pb.p, tol=pb.tol, precision=precision, workgroups=args.workgroups,
                        validate=1, **kw)
+    log(f"{args.workload}: {args.warmup} warmup + {args.steps} timed solves")
     ms, st = time_solves(solver, pb.t, b, u, args.steps, args.warmup)
+    log(f"{args.workload}: {ms:.3f} ms per solve")
     status = pk.lib().phipm_last_status()
     if status != 0:
         raise pk.PhipmError(status, "timed solve")
@@ -221,7 +238,7 @@ def run_single(args, with_headline):
             "n": pb.n, "nnz": int(pb.A.nnz), "p": pb.p, "t": pb.t, "tol": pb.tol,
             "workgroups": st["workgroups"], "lanczos": st["lanczos"],
             "csr_values": "f32" if vdt == np.float32 else "f64",
-            "method": f"phip (m fixed at {args.fixed_m})" if args.fixed_m > 0 else "phipm",
+            "method": method_name(args),
             "solve_stats": {k: st[k] for k in ("steps", "rejected", "matvecs", "expms",
                                                 "m_last", "fp64_steps",
                                                 "fp32_error_estimate")},
@@ -245,6 +262,7 @@ def run_single(args, with_headline):
     if traffic_src:
         line["roofline"]["traffic_source"] = traffic_src
     if not args.no_cpu:
+        log(f"{args.workload}: CPU oracle")
         ref, base = oracle_reference(pb)
         line["err_vs_oracle"] = rel_err(u_gpu, ref)
         line["cpu_baseline"] = base
@@ -284,7 +302,9 @@ def run_calls_block(args, calls, warmup, oracle_calls=True):
     check = sorted(set(np.linspace(0, calls - 1, min(calls, 6)).astype(int).tolist()))
     res, outs = {}, {}
     for name, basis, learned, warm in CALL_VARIANTS:
-        s = pk.Solver(Ad, 2, tol=tol, precision=pk.FP32_BASIS if basis == "fp32" else pk.FP64)
+        log(f"call sequence: variant {name}, {calls} calls")
+        s = pk.Solver(Ad, 2, tol=tol, precision=pk.FP32_BASIS if basis == "fp32" else pk.FP64,
+                      **fixed_m_kw(args))
         hist = torch.zeros(4, dtype=torch.float64, device="cuda")
         if warm:
             s.opts.history = hist.data_ptr()
@@ -316,6 +336,7 @@ def run_calls_block(args, calls, warmup, oracle_calls=True):
                 outs[name][c] = u.cpu().numpy()
         res[name] = {"ms_per_call": ms, "calls_per_s": 1e3 / ms, **tot}
     block = {"workload": WORKLOADS["reaction2d-1024-calls"][1], "calls": calls,
+             "method": method_name(args),
              "timed_variant": "learned-fp32", "baseline_variant": "plain-fp64-cold",
              "variants": res}
     block["speedup_vs_plain_fp64"] = (res["learned-fp32"]["calls_per_s"] /
@@ -325,6 +346,7 @@ def run_calls_block(args, calls, warmup, oracle_calls=True):
         oracle.build(force=False)
         errs = {name: [] for name in res}
         for c in check:
+            log(f"call sequence: CPU oracle on call {c}")
             ref, _ = oracle.phipm(t, A, W.config5_b(c, n), tol=tol)
             for name in res:
                 errs[name].append(rel_err(outs[name][c], ref))
@@ -344,7 +366,8 @@ def run_calls(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": v["ms_per_call"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-basis/f64", "data": "synthetic",
-        "config": {"workload": block["workload"], "n": 1048576, "calls": args.steps,
+        "config": {"workload": block["workload"], "method": block["method"], "n": 1048576,
+                   "calls": args.steps,
                    "variants": block["variants"],
                    "speedup_vs_plain_fp64": block["speedup_vs_plain_fp64"]},
     }
@@ -443,10 +466,11 @@ def run_batch(args):
     precision = pk.FP32_BASIS if args.precision == "fp32" else pk.FP64
     t0 = time.perf_counter()
     plan = pk.Plan(As, [pb.p for pb in probs], [pb.t for pb in probs], bs, us, tol=probs[0].tol,
-                   precision=precision, workgroups=args.workgroups,
+                   precision=precision, workgroups=args.workgroups, **fixed_m_kw(args),
                    plan_opts=pk.default_plan_opts(autotune=0 if args.no_tune else 1, graph=1))
     create_s = time.perf_counter() - t0
     info = plan.info()
+    log(f"batch: plan made in {create_s:.1f} s; {args.warmup} warmup + {args.steps} timed runs")
     for _ in range(max(1, args.warmup)):
         plan.execute()
     torch.cuda.synchronize()
@@ -473,6 +497,7 @@ def run_batch(args):
         "data": "synthetic",
         "config": {
             "workload": WORKLOADS["convdiff2d-batch256"][1],
+            "method": method_name(args),
             "instances": len(probs), "rows": int(sum(pb.n for pb in probs)),
             "nnz": int(sum(pb.A.nnz for pb in probs)),
             "plan": {k: info[k] for k in ("teams", "class_size", "class_teams", "graph",
@@ -494,6 +519,7 @@ def run_batch(args):
         },
     }
     if not args.no_cpu:
+        log("batch: CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline_batch(probs, st)
     print(json.dumps(line), flush=True)
     plan.close()
@@ -518,8 +544,8 @@ def main():
                          "when every value is exact in float32)")
     ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the autotuner")
     ap.add_argument("--fixed-m", type=int, default=0, metavar="M",
-                    help="single solves: the paper's phip (Krylov dimension fixed at M, only tau "
-                         "adapted) instead of phipm")
+                    help="the paper's phip (Krylov dimension fixed at M, only tau adapted) "
+                         "instead of phipm, for any workload but the integrator")
     ap.add_argument("--tol", type=float, default=0.0,
                     help="single solves: override the workload's tolerance (a different "
                          "workload: named in config.tol)")
