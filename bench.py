@@ -261,6 +261,13 @@ def run_single(args, with_headline):
     }
     if traffic_src:
         line["roofline"]["traffic_source"] = traffic_src
+    if st.get("krylov_seconds", 0.0) > 0.0:
+        # the Krylov builds alone (CSR products + orthogonalisation), timed on
+        # the device by the solve's first workgroup in an untimed solve
+        kb, ks = st["krylov_bytes_ref"], st["krylov_seconds"]
+        line["roofline"]["krylov_phase"] = {
+            "bytes_ref": kb, "seconds": ks, "achieved": kb / ks / 1e9,
+            "frac": kb / ks / 1e9 / HBM_PEAK_GBS, "share_of_solve": ks / sec}
     if not args.no_cpu:
         log(f"{args.workload}: CPU oracle")
         ref, base = oracle_reference(pb)

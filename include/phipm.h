@@ -147,6 +147,11 @@ typedef struct {
                                   the CSR product plus (4(j+1) + 8) vectors (Arnoldi) or
                                   16 vectors (Lanczos); per step p products and 3p vectors
                                   for eq. wrecurrence and (p + m + 2) vectors for eq. step */
+  double krylov_bytes_ref;     /* the part of bytes_ref spent building Krylov bases (the
+                                  CSR products and the orthogonalisation, Algorithms 1-2) */
+  double krylov_seconds;       /* device time spent building Krylov bases, from the
+                                  constant-rate wall clock of the solve's first workgroup
+                                  (every workgroup of a solve builds in lock step) */
 } phipm_stats;
 
 void phipm_default_opts(phipm_opts* opts);

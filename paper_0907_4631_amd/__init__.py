@@ -58,7 +58,8 @@ class Stats(C.Structure):
                 ("pad_", C.c_int32), ("bytes", C.c_double), ("phi_ratio_max", C.c_double),
                 ("precision_rejects", C.c_int64), ("fp32_error_estimate", C.c_double),
                 ("fp64_steps", C.c_int32), ("trace_len", C.c_int32),
-                ("proposals", C.c_int64), ("bytes_ref", C.c_double)]
+                ("proposals", C.c_int64), ("bytes_ref", C.c_double),
+                ("krylov_bytes_ref", C.c_double), ("krylov_seconds", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -816,9 +816,10 @@ int phipm_plan_stats(phipm_plan* pl, phipm_stats* stats) {
       hipStreamSynchronize(s) != hipSuccess)
     return PHIPM_EHIP;
   int first = PHIPM_OK;
+  const double tick_s = wall_tick_seconds(pl->device);
   for (int i = 0; i < pl->count; ++i) {
     const int st = ab ? PHIPM_EABORT : hs[i].status;
-    copy_stats(hs[i], st, &stats[i]);
+    copy_stats(hs[i], st, tick_s, &stats[i]);
     if (first == PHIPM_OK && st != PHIPM_OK) first = st;
   }
   return first;

@@ -20,6 +20,8 @@ static_assert(sizeof(TraceStep) == sizeof(phipm_trace_step), "TraceStep mirrors 
 static_assert(offsetof(TraceStep, H) == offsetof(phipm_trace_step, H), "trace layout");
 static_assert(offsetof(Stats, proposals) == offsetof(phipm_stats, proposals), "stats layout");
 static_assert(offsetof(Stats, bytes_ref) == offsetof(phipm_stats, bytes_ref), "stats layout");
+static_assert(offsetof(Stats, krylov_ticks) == offsetof(phipm_stats, krylov_seconds),
+              "stats layout");
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 inline long long pad64(long long x) { return (x + 63) / 64 * 64; }
@@ -84,7 +86,16 @@ inline bool overlaps(const void* a, size_t na, const void* c, size_t nc) {
   return x < y + nc && y < x + na;
 }
 
-inline void copy_stats(const Stats& hs, int status, phipm_stats* s) {
+// Seconds per tick of the device's constant-rate wall clock (wall_clock64).
+inline double wall_tick_seconds(int device) {
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0)
+    return 0.0;
+  return 1e-3 / (double)khz;
+}
+
+// tick_s: seconds per wall-clock tick of the device the statistics come from.
+inline void copy_stats(const Stats& hs, int status, double tick_s, phipm_stats* s) {
   s->steps = hs.steps;
   s->rejected = hs.rejected;
   s->matvecs = hs.matvecs;
@@ -106,6 +117,8 @@ inline void copy_stats(const Stats& hs, int status, phipm_stats* s) {
   s->trace_len = hs.trace_len;
   s->proposals = hs.proposals;
   s->bytes_ref = hs.bytes_ref;
+  s->krylov_bytes_ref = hs.krylov_bytes_ref;
+  s->krylov_seconds = hs.krylov_ticks * tick_s;
 }
 
 }  // namespace pkr

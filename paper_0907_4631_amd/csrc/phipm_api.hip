@@ -159,6 +159,7 @@ struct DeviceInfo {
   int cus = 0;
   int coresident[4] = {0, 0, 0, 0};  // cooperative grid limit per solve_kernel() index
   unsigned long long spin_ticks = 0;
+  double tick_s = 0.0;  // seconds per wall-clock tick
   bool ok = false;
 };
 
@@ -185,6 +186,7 @@ const DeviceInfo* device_info() {
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
       khz = 100000;
     d.spin_ticks = (unsigned long long)khz * 1000ull * 20ull;  // 20 s per wait
+    d.tick_s = wall_tick_seconds(dev);
     d.ok = true;
   }
   return &d;
@@ -397,7 +399,7 @@ int phipm(double t, const phipm_csr* A, int p, const double* b, const phipm_opts
         hipMemcpyAsync(&hc, ctl, sizeof(TeamCtl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return fail(PHIPM_EHIP);
-    copy_stats(hs, hc.abort ? PHIPM_EABORT : hs.status, stats);
+    copy_stats(hs, hc.abort ? PHIPM_EABORT : hs.status, d->tick_s, stats);
     stats->workgroups = G;
     return stats->status;
   }

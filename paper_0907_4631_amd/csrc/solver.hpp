@@ -85,6 +85,8 @@ struct Stats {              // mirrors phipm_stats
   int fp64_steps, trace_len;
   long long proposals;      // steps seeded by the proposer
   double bytes_ref;         // the same passes priced by the plain CGS2 byte model
+  double krylov_bytes_ref;  // the Krylov builds' part of bytes_ref
+  double krylov_ticks;      // wall-clock ticks workgroup 0 spent in Krylov builds
 };
 
 struct State {
@@ -92,6 +94,9 @@ struct State {
   double t, tau, beta;
   double bytes;             // algorithmic HBM bytes so far
   double bytes_ref;         // bytes of the plain CGS2 model (reference byte count)
+  double krylov_bytes_ref;  // the Krylov builds' part of bytes_ref
+  unsigned long long krylov_ticks;  // wall-clock ticks workgroup 0 spent in Krylov builds
+  unsigned long long krylov_t0;     // wall clock at the start of the current build
   double unorm;             // ||u_k||_2 of the current state
   double rho_max;           // largest ||beta y|| / ||u_k|| seen (FP32 basis)
   long long prec_rejects;   // FP32 attempts repeated with the FP64 basis
@@ -918,6 +923,8 @@ __device__ __forceinline__ bool build_basis(const Team& tm, const Problem& P, co
                                             const double* wp, double beta, int rb, int re,
                                             Shared& sh) {
   kc.products = 0;
+  // the start time goes to the state, not a register held across the loop
+  if (tm.rank == 0 && threadIdx.x == 0) w.st->krylov_t0 = wall_clock64();
   while (!kc.broke && kc.have < target && kc.have < P.n) {
     const bool ok =
         kc.have == 0
@@ -929,9 +936,13 @@ __device__ __forceinline__ bool build_basis(const Team& tm, const Problem& P, co
   }
   if (!krylov_finalize<TB>(tm, P, w, lanczos, bd_tol, kc, rb, re, sh)) return false;
   if (kc.have >= P.n) kc.broke = 1;  // the whole space: exact for any tau
-  if (tm.rank == 0 && threadIdx.x == 0 && kc.products > 0)
-    w.st->bytes_ref +=
+  if (tm.rank == 0 && threadIdx.x == 0 && kc.products > 0) {
+    const double b =
         krylov_ref_bytes(P, sizeof(VT), sizeof(TB), kc.have - kc.products, kc.products, lanczos);
+    w.st->bytes_ref += b;
+    w.st->krylov_bytes_ref += b;
+    w.st->krylov_ticks += wall_clock64() - w.st->krylov_t0;
+  }
   return true;
 }
 
@@ -1207,6 +1218,8 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       st->bytes = (check_sym ? 2.0 : 1.0) * (sizeof(VT) + 4.0) * P.nnz + 4.0 * (n + 1.0) +
                   8.0 * n * (p + 1.0);
       st->bytes_ref = 0.0;
+      st->krylov_bytes_ref = 0.0;
+      st->krylov_ticks = 0;
     }
     if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
   }
@@ -1445,6 +1458,8 @@ finish:
     o->setup_flags = st->setup_flags;
     o->bytes = st->bytes;
     o->bytes_ref = st->bytes_ref;
+    o->krylov_bytes_ref = st->krylov_bytes_ref;
+    o->krylov_ticks = (double)st->krylov_ticks;
     o->rho_max = st->rho_max;
     o->prec_rejects = st->prec_rejects;
     o->fp32_err = st->fp32_err;
