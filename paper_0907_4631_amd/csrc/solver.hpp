@@ -150,6 +150,8 @@ struct Shared {
   union {
     SpmvSmem<double> sm64;
     SpmvSmem<float> sm32;
+    SpmvPipe<double> pipe64;
+    SpmvPipe<float> pipe32;
     double dense[DENSE_LDS];  // workgroup 0's small-matrix work
     struct {
       double wpart[NWAVES][KMAX];  // per-wave partial dot products (phase_dots2)
@@ -219,6 +221,12 @@ template <>
 __device__ __forceinline__ SpmvSmem<double>& smem_for<double>(Shared& sh) { return sh.sm64; }
 template <>
 __device__ __forceinline__ SpmvSmem<float>& smem_for<float>(Shared& sh) { return sh.sm32; }
+template <typename T>
+__device__ __forceinline__ SpmvPipe<T>& pipe_for(Shared& sh);
+template <>
+__device__ __forceinline__ SpmvPipe<double>& pipe_for<double>(Shared& sh) { return sh.pipe64; }
+template <>
+__device__ __forceinline__ SpmvPipe<float>& pipe_for<float>(Shared& sh) { return sh.pipe32; }
 
 // Block sums over own rows (float64): blk[k] = V[:, i0+k] . w for k < K,
 // and when with_u also blk[K+k] = V[:, i0+k] . u, blk[2K] = u . u,
@@ -361,6 +369,26 @@ struct KrylovCtl {
   int products;                         // products with A made by this build
 };
 
+// y = A x over the workgroup's rows [rb, re): ld(c) gives x_c in float64,
+// st(r, y_r) takes each row's sum.  Double-buffered DMA staging (the next
+// tile's indices and float32 values load while this tile gathers); float64
+// values of long rows (more than six entries on average) use staged tiles
+// instead, since the pipelined path reads float64 values row by row.
+template <typename VT, typename Load, typename Store>
+__device__ __forceinline__ void csr_product(const Problem& P, const VT* val, int rb, int re,
+                                            Shared& sh, Load ld, Store st) {
+  if (sizeof(VT) == 8 && (long long)P.nnz > 6ll * P.n) {
+    for (int r0 = rb; r0 < re; r0 += BLOCK) {
+      const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
+      const double acc = spmv_tile<VT, double, 8>(P.rp, P.ci, val, r0, r1, smem_for<VT>(sh), ld);
+      const int r = r0 + threadIdx.x;
+      if (r < r1) st(r, acc);
+    }
+  } else {
+    spmv_pipelined<VT, double, 8>(P.rp, P.ci, val, rb, re, pipe_for<VT>(sh), ld, st);
+  }
+}
+
 // Second pass of the candidate in U against columns [zb, j) of V and its
 // norm.  The coefficients s go to sh.h1[0..K) (the caller adds them to
 // column j-1 of H, with H[j][j-1] = beta).  beta comes from Pythagoras,
@@ -424,28 +452,24 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
   T* Wv = w.y1;
   const bool uf = kc.u_final != 0;
   // P1: w = A u_j
-  {
+  if (seed) {
     T* v0 = w.V;
     for (int r0 = rb; r0 < re; r0 += BLOCK) {
       const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
-      double acc;
-      if (seed) {
-        auto ld = [&](int c) -> double { return (double)T(seed[c] * seed_scale); };
-        acc = spmv_tile<VT, double>(P.rp, P.ci, valT, r0, r1, smem_for<VT>(sh), ld);
-      } else {
-        auto ld = [&](int c) -> double { return (double)U[c]; };
-        acc = spmv_tile<VT, double, 8>(P.rp, P.ci, valT, r0, r1, smem_for<VT>(sh), ld);
-      }
+      auto ld = [&](int c) -> double { return (double)T(seed[c] * seed_scale); };
+      const double acc = spmv_tile<VT, double>(P.rp, P.ci, valT, r0, r1, smem_for<VT>(sh), ld);
       const int r = r0 + threadIdx.x;
       if (r < r1) {
         Wv[r] = T(sgn * acc);
-        if (seed) {
-          const T v = T(seed[r] * seed_scale);
-          v0[r] = v;
-          U[r] = v;
-        }
+        const T v = T(seed[r] * seed_scale);
+        v0[r] = v;
+        U[r] = v;
       }
     }
+  } else {
+    auto ld = [&](int c) -> double { return (double)U[c]; };
+    auto st = [&](int r, double acc) { Wv[r] = T(sgn * acc); };
+    csr_product<VT>(P, valT, rb, re, sh, ld, st);
   }
   // P2: one reduction over the window [zb, j)
   const int zb = lanczos ? (j > 2 ? j - 2 : 0) : 0;
@@ -1270,21 +1294,17 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
         double* wj = w.W + (long long)(j - 1) * w.ldw;
         double nrm = 0.0;
         auto ld = [&](int c) -> double { return wprev[c]; };
-        for (int r0 = rb; r0 < re; r0 += BLOCK) {
-          const int r1 = r0 + BLOCK < re ? r0 + BLOCK : re;
-          double acc = spmv_tile<VT, double, 8>(P.rp, P.ci, val, r0, r1, smem_for<VT>(sh), ld);
-          const int r = r0 + tid;
-          if (r < r1) {
-            double s = sgn * acc;
-            double f = 1.0;  // t^l / l!, times the sign of b_{j+l}
-            for (int l = 0; l <= p - j; ++l) {
-              s += (((j + l) & 1) ? sgn * f : f) * P.b[(long long)(j + l) * P.ldb + r];
-              f *= t / (double)(l + 1);
-            }
-            wj[r] = s;
-            nrm += s * s;
+        auto stw = [&](int r, double acc) {
+          double s = sgn * acc;
+          double f = 1.0;  // t^l / l!, times the sign of b_{j+l}
+          for (int l = 0; l <= p - j; ++l) {
+            s += (((j + l) & 1) ? sgn * f : f) * P.b[(long long)(j + l) * P.ldb + r];
+            f *= t / (double)(l + 1);
           }
-        }
+          wj[r] = s;
+          nrm += s * s;
+        };
+        csr_product<VT>(P, val, rb, re, sh, ld, stw);
         if (tm.rank == 0 && tid == 0) {
           st->bytes += spmv_bytes(P, sizeof(VT), 8.0) + 8.0 * n * (p - j + 1.0);
           st->bytes_ref += spmv_bytes(P, sizeof(VT), 8.0) + 3.0 * 8.0 * n;  // w-recurrence
@@ -1294,7 +1314,9 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
           block_reduce<1>(a1, RED_SUM, sh.blk);
           if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
         } else {
-          if (!team_sync(tm, nullptr, 0, RED_SUM, nullptr)) return SOLVE_ABORTED;
+          // the next product reads w_j only in the rows of the slots this
+          // workgroup depends on
+          if (!team_neighbor_sync(tm, sh.dep_lo, sh.dep_hi)) return SOLVE_ABORTED;
         }
       }
       if (p == 0) {

@@ -279,8 +279,10 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
   // group sums rotate over TEAM_GBUF buffers by epoch: a leader may write a
   // later sync's sums while a slower workgroup of another group still reads
   // this one's, as long as only neighbour synchronisations (which do not
-  // wait for that workgroup) lie between the two; the solver never has more
-  // than one in a row
+  // wait for that workgroup) lie between the two.  Between two reductions of
+  // more than eight values the solver has at most one (the w-recurrence's
+  // run of them ends in a one-value reduction, which waits for every
+  // workgroup)
   double* gsum =
       tm.partials + ((size_t)tm.size + (size_t)(e % (unsigned)TEAM_GBUF) * ngroups) * PS;
   const int grp = tm.rank / TEAM_GROUP;
