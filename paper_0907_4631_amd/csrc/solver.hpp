@@ -420,7 +420,7 @@ __device__ __forceinline__ double second_pass(const Team& tm, const Work<T>& w, 
       acc[0] += (double)ut * (double)ut;
     }
     block_reduce<1>(acc, RED_SUM, sh.blk);
-    if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.qv)) return -1.0;
+    if (!team_sync<true>(tm, sh.blk, 1, RED_SUM, sh.qv)) return -1.0;
     b2 = sh.qv[0];
     *applied = true;
     __syncthreads();  // sh.qv is reused by the caller
@@ -475,7 +475,7 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
   const int zb = lanczos ? (j > 2 ? j - 2 : 0) : 0;
   const int K = j - zb;
   phase_dots2<T>(w.V, w.ldv, zb, K, U, Wv, !uf, rb, re, sh);
-  if (!team_sync(tm, sh.blk, 2 * K + 2, RED_SUM, sh.red)) return false;
+  if (!team_sync<true>(tm, sh.blk, 2 * K + 2, RED_SUM, sh.red)) return false;
   const double a = sh.red[2 * K], c = sh.red[2 * K + 1];
   // z -> sh.red[0..K), s -> sh.h1[0..K)
   for (int k = threadIdx.x; k < K; k += BLOCK) sh.h1[k] = uf ? 0.0 : sh.red[K + k];
@@ -612,7 +612,7 @@ __device__ __forceinline__ bool krylov_finalize(const Team& tm, const Problem& P
   const int zb = lanczos ? (j > 2 ? j - 2 : 0) : 0;
   const int K = j - zb;
   phase_dots2<T>(w.V, w.ldv, zb, K, U, U, true, rb, re, sh);
-  if (!team_sync(tm, sh.blk + K, K + 1, RED_SUM, sh.red)) return false;
+  if (!team_sync<true>(tm, sh.blk + K, K + 1, RED_SUM, sh.red)) return false;
   // sh.red[0..K) = V^T u, sh.red[K] = u.u
   const double a = sh.red[K];
   for (int k = threadIdx.x; k < K; k += BLOCK) sh.h1[k] = sh.red[k];

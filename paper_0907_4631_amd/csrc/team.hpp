@@ -163,6 +163,17 @@ __device__ __forceinline__ void st_relaxed(unsigned* p, unsigned v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Agent-coherent data accesses (relaxed agent-scope atomics: written
+// through to, and read from, the level shared by all XCDs) for the values of
+// a light reduction, which publishes nothing else and so needs no cache-wide
+// write-back or invalidation.
+__device__ __forceinline__ void st_coh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Reduce src rows: dst[k*dld+di] = op over src[k*ld + 0..cnt) for k < K.
 __device__ __forceinline__ void reduce_rows(const double* src, int ld, int cnt, int K, int op,
                                             double* dst, int dld, int di) {
@@ -178,9 +189,11 @@ __device__ __forceinline__ void reduce_rows(const double* src, int ld, int cnt, 
 
 // Waves 0..ceil(cnt/64)-1 of the calling workgroup wait until the cnt flags
 // at flags, FLAG_STRIDE apart (one per lane), have all reached epoch e; the
-// workgroup then takes an agent-scope acquire.  Returns false (in every
-// thread) if the team was aborted or a wait ran out of time (then it sets
-// abort).
+// workgroup then takes an agent-scope acquire (not when LIGHT: the caller
+// reads only agent-coherent data published with the flags).  Returns false
+// (in every thread) if the team was aborted or a wait ran out of time (then
+// it sets abort).
+template <bool LIGHT = false>
 __device__ __forceinline__ bool wait_flags(const Team& tm, const unsigned* flags, int cnt,
                                            unsigned e) {
   __shared__ int s_bad;
@@ -207,8 +220,10 @@ __device__ __forceinline__ bool wait_flags(const Team& tm, const unsigned* flags
     if (bad && lane == 0) s_bad = 1;
   }
   __syncthreads();
-  if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  __syncthreads();
+  if (!LIGHT) {
+    if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+  }
   return s_bad == 0;
 }
 
@@ -228,6 +243,12 @@ __device__ __forceinline__ bool wait_flags(const Team& tm, const unsigned* flags
 //    in group order (no further publication step).
 // Returns false if the team was aborted (a wait ran past its time budget);
 // callers then leave the kernel.
+// LIGHT: the values travel by agent-coherent stores and loads and the flags
+// carry no release or acquire, so the sync publishes nothing but the values
+// (no write-back of this workgroup's other global writes, no invalidation
+// before later reads of other workgroups' data).  For reductions whose
+// surrounding code reads only its own rows until a full synchronisation.
+template <bool LIGHT = false>
 __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int K, int op,
                                           double* out) {
   __shared__ unsigned s_epoch;
@@ -241,38 +262,49 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
   const int PS = KMAX;
   const int ngroups = (tm.size + TEAM_GROUP - 1) / TEAM_GROUP;
   unsigned* my = tm.arr + (size_t)tm.rank * FLAG_STRIDE;
-  for (int k = tid; k < K; k += BLOCK) tm.partials[(size_t)tm.rank * PS + k] = blk[k];
+  for (int k = tid; k < K; k += BLOCK) {
+    double* dst = tm.partials + (size_t)tm.rank * PS + k;
+    if (LIGHT) st_coh(dst, blk[k]);
+    else *dst = blk[k];
+  }
+  // (LIGHT: every wave's coherent stores have completed at this barrier)
+  if (LIGHT) __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) {
     const unsigned e = ld_relaxed(my) + 1u;  // this workgroup's own epoch count
     s_epoch = e;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (!LIGHT) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     st_relaxed(my, e);
   }
   __syncthreads();
   const unsigned e = s_epoch;
   if (K <= 8) {
     if (tm.rank == 0) {
-      if (!wait_flags(tm, tm.arr, tm.size, e)) return false;
+      if (!wait_flags<LIGHT>(tm, tm.arr, tm.size, e)) return false;
       const int lane = tid % WAVE, wv = tid / WAVE;
       for (int k = wv; k < K; k += NWAVES) {
         double a = (op == RED_SUM) ? 0.0 : -INFINITY;
         for (int r = lane; r < tm.size; r += WAVE) {
-          const double v = tm.partials[(size_t)r * PS + k];
+          const double* src = tm.partials + (size_t)r * PS + k;
+          const double v = LIGHT ? ld_coh(src) : *src;
           a = (op == RED_SUM) ? a + v : nanmax(a, v);
         }
         a = (op == RED_SUM) ? wave_sum(a) : wave_max(a);
-        if (lane == 0) tm.result[k] = a;
+        if (lane == 0) {
+          if (LIGHT) st_coh(tm.result + k, a);
+          else tm.result[k] = a;
+        }
       }
+      if (LIGHT) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (tid == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (!LIGHT) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         st_relaxed(tm.gen, e);
       }
     } else {
-      if (!wait_flags(tm, tm.gen, 1, e)) return false;
+      if (!wait_flags<LIGHT>(tm, tm.gen, 1, e)) return false;
     }
-    for (int k = tid; k < K; k += BLOCK) out[k] = tm.result[k];
+    for (int k = tid; k < K; k += BLOCK) out[k] = LIGHT ? ld_coh(tm.result + k) : tm.result[k];
     __syncthreads();
     return true;
   }
@@ -289,32 +321,39 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
   const int g0 = grp * TEAM_GROUP;
   const int gsz = tm.size - g0 < TEAM_GROUP ? tm.size - g0 : TEAM_GROUP;
   if (tm.rank == g0) {
-    if (!wait_flags(tm, tm.arr + (size_t)g0 * FLAG_STRIDE, gsz, e)) return false;
+    if (!wait_flags<LIGHT>(tm, tm.arr + (size_t)g0 * FLAG_STRIDE, gsz, e)) return false;
     for (int k = tid; k < K; k += BLOCK) {
       double v[TEAM_GROUP];
 #pragma unroll
-      for (int r = 0; r < TEAM_GROUP; ++r)
-        v[r] = r < gsz ? tm.partials[(size_t)(g0 + r) * PS + k] : v[0];
+      for (int r = 0; r < TEAM_GROUP; ++r) {
+        const double* src = tm.partials + (size_t)(g0 + r) * PS + k;
+        v[r] = r < gsz ? (LIGHT ? ld_coh(src) : *src) : 0.0;
+      }
       double a = v[0];
 #pragma unroll
       for (int r = 1; r < TEAM_GROUP; ++r)
         if (r < gsz) a = (op == RED_SUM) ? a + v[r] : nanmax(a, v[r]);
-      gsum[(size_t)grp * PS + k] = a;
+      if (LIGHT) st_coh(gsum + (size_t)grp * PS + k, a);
+      else gsum[(size_t)grp * PS + k] = a;
     }
+    if (LIGHT) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (!LIGHT) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       st_relaxed(tm.garr + (size_t)grp * FLAG_STRIDE, e);
     }
   }
-  if (!wait_flags(tm, tm.garr, ngroups, e)) return false;
+  if (!wait_flags<LIGHT>(tm, tm.garr, ngroups, e)) return false;
   for (int k = tid; k < K; k += BLOCK) {
     double a = 0.0;
     bool first = true;
     for (int gb = 0; gb < ngroups; gb += 16) {
       double v[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = gb + q < ngroups ? gsum[(size_t)(gb + q) * PS + k] : 0.0;
+      for (int q = 0; q < 16; ++q) {
+        const double* src = gsum + (size_t)(gb + q) * PS + k;
+        v[q] = gb + q < ngroups ? (LIGHT ? ld_coh(src) : *src) : 0.0;
+      }
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         if (gb + q < ngroups) {
