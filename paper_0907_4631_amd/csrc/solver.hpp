@@ -369,6 +369,15 @@ struct KrylovCtl {
   int products;                         // products with A made by this build
 };
 
+// Store written through to the level shared by all XCDs (an agent-scope
+// relaxed atomic store): the vectors a step streams out are then not left
+// dirty in this XCD's L2 for the next synchronisation's release to write
+// back.
+template <typename T>
+__device__ __forceinline__ void st_wt(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // y = A x over the workgroup's rows [rb, re): ld(c) gives x_c in float64,
 // st(r, y_r) takes each row's sum.  Double-buffered DMA staging (the next
 // tile's indices and float32 values load while this tile gathers); float64
@@ -468,7 +477,7 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
     }
   } else {
     auto ld = [&](int c) -> double { return (double)U[c]; };
-    auto st = [&](int r, double acc) { Wv[r] = T(sgn * acc); };
+    auto st = [&](int r, double acc) { st_wt(Wv + r, T(sgn * acc)); };
     csr_product<VT>(P, valT, rb, re, sh, ld, st);
   }
   // P2: one reduction over the window [zb, j)
@@ -586,8 +595,8 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
     }
     const double ur = (double)U[r];
     const T vjt = uf ? T(ur) : T((ur - vs) * ib);
-    if (!uf) vj[r] = vjt;
-    U[r] = T((double)Wv[r] * ib - vq - tj * (double)vjt);
+    if (!uf) st_wt(vj + r, vjt);
+    st_wt(U + r, T((double)Wv[r] * ib - vq - tj * (double)vjt));
   }
   // the next product reads u_{j+1} only in the rows of the slots this
   // workgroup depends on
@@ -1010,7 +1019,7 @@ __device__ __forceinline__ double step_update(const Problem& P, const Work<TB>& 
       for (; k < mu; ++k) s += sh.yb[k] * (double)vp[(long long)k * w.ldv];
       if (use_corr) s += sh.yb[mu] * (double)vp[(long long)mu * w.ldv];
     }
-    P.u[r] = s;
+    st_wt(P.u + r, s);
     un += s * s;
   }
   return un;
@@ -1301,7 +1310,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
             s += (((j + l) & 1) ? sgn * f : f) * P.b[(long long)(j + l) * P.ldb + r];
             f *= t / (double)(l + 1);
           }
-          wj[r] = s;
+          st_wt(wj + r, s);
           nrm += s * s;
         };
         csr_product<VT>(P, val, rb, re, sh, ld, stw);
