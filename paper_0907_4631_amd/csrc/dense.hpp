@@ -11,18 +11,62 @@ namespace pkr {
 
 constexpr int DENSE_LDS = 17408;  // doubles of LDS available to the dense routines
 
+// Largest padded order (a multiple of 16) whose product runs on the matrix
+// cores with both operands in LDS.
+constexpr int MFMA_NMAX = 80;
+static_assert(2 * MFMA_NMAX * MFMA_NMAX <= DENSE_LDS, "MFMA operands fit the dense LDS");
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 // C = A B for N x N row-major matrices in device memory (an L2-resident
-// scratch).  When both operands fit, A is staged transposed and B as is in
-// LDS, zero-padded to a multiple of 4, and every thread accumulates a 4 x 4
-// block of C in registers from 16-byte LDS reads.  Up to N = 128 (at most one
-// 4 x 4 block per thread) the same runs over panels of MM_KC values of k
-// staged in turn; beyond that, one output entry per thread straight from
-// memory.
+// scratch).  Up to N = MFMA_NMAX the matrix cores form 16 x 16 blocks of C
+// from operands staged in LDS.  Above that, while both operands fit, A is
+// staged transposed and B as is in LDS, zero-padded to a multiple of 4, and
+// every thread accumulates a 4 x 4 block of C in registers from 16-byte LDS
+// reads.  Up to N = 128 (at most one 4 x 4 block per thread) the same runs
+// over panels of MM_KC values of k staged in turn; beyond that, one output
+// entry per thread straight from memory.
 __device__ __forceinline__ void wg_matmul(int N, const double* __restrict__ A,
                                           const double* __restrict__ B, double* __restrict__ C,
                                           double* L) {
   const int NN = N * N;
   const int N4 = (N + 3) & ~3;
+  const int N16 = (N + 15) & ~15;
+  if (N16 <= MFMA_NMAX) {
+    // matrix cores: both operands in LDS as At[k][i] = A[i][k] and Bs[k][j],
+    // zero-padded to a multiple of 16; each wavefront forms 16 x 16 blocks
+    // of C with v_mfma_f64_16x16x4f64, four values of k per instruction.
+    // Lane l supplies A[i0 + l%16][k + l/16] and B[k + l/16][j0 + l%16] and
+    // receives C[i0 + l/16 + 4r][j0 + l%16] in element r of the result.
+    double* At = L;
+    double* Bs = L + N16 * N16;
+    for (int e = threadIdx.x; e < N16 * N16; e += BLOCK) {
+      const int r = e / N16, c = e - r * N16;
+      const bool in = r < N && c < N;
+      At[c * N16 + r] = in ? A[r * N + c] : 0.0;
+      Bs[e] = in ? B[r * N + c] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int nb = N16 >> 4;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int blk = wv; blk < nb * nb; blk += NWAVES) {  // uniform per wavefront
+      const int i0 = (blk / nb) * 16, j0 = (blk - (blk / nb) * nb) * 16;
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      const double* pa = At + lk * N16 + i0 + lr;
+      const double* pb = Bs + lk * N16 + j0 + lr;
+#pragma unroll 4
+      for (int k = 0; k < N16; k += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[k * N16], pb[k * N16], acc, 0, 0, 0);
+      const int j = j0 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + lk + 4 * r;
+        if (i < N && j < N) C[i * N + j] = acc[r];
+      }
+    }
+    __syncthreads();
+    return;
+  }
   if (2 * N4 * N4 <= DENSE_LDS) {
     double* At = L;             // At[k][i] = A[i][k]
     double* Bs = L + N4 * N4;   // Bs[k][j] = B[k][j]

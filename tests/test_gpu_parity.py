@@ -92,9 +92,10 @@ def test_spmv_matches_oracle(pk, case):
     assert np.all(np.abs(y.cpu().numpy() - ref) <= 1e-14 * scale + 1e-300)
 
 
-@pytest.mark.parametrize("N,scale", [(1, 3.0), (2, 0.5), (5, 40.0), (17, 1.0), (41, 25.0),
-                                     (42, 25.0), (44, 12.0), (45, 9.0),
-                                     (70, 200.0), (92, 30.0), (93, 8.0), (103, 50.0),
+@pytest.mark.parametrize("N,scale", [(1, 3.0), (2, 0.5), (5, 40.0), (16, 4.0), (17, 1.0),
+                                     (41, 25.0), (42, 25.0), (44, 12.0), (45, 9.0),
+                                     (64, 30.0), (70, 200.0), (80, 60.0), (81, 10.0),
+                                     (92, 30.0), (93, 8.0), (103, 50.0),
                                      (128, 5.0), (129, 2.0), (137, 3.0)])
 def test_expm_matches_oracle(pk, N, scale):
     say("expm case", N, scale)
