@@ -201,6 +201,196 @@ __device__ __forceinline__ void wg_matcols(int N, const double* __restrict__ A,
 // (computed exactly by taylor_theta.py beside these sources).
 constexpr double TAYLOR18_THETA = 1.0908637192900361;
 
+// Largest order whose whole exponential stays in LDS: two padded matrices,
+// and at most two 16 x 16 blocks of each product per wavefront.
+constexpr int EXPM_LDS_N = 80;
+static_assert(2 * EXPM_LDS_N * EXPM_LDS_N <= DENSE_LDS, "two padded matrices fit the dense LDS");
+static_assert((EXPM_LDS_N / 16) * (EXPM_LDS_N / 16) <= 2 * NWAVES, "two blocks per wavefront");
+
+// One 16 x 16 block of At^T Bs on the matrix cores: At[k][i] and Bs[k][j] in
+// LDS with row stride N16; lane l receives rows i0 + l/16 + 4r, column
+// j0 + l%16 in element r.
+__device__ __forceinline__ dbl4 mfma_block(const double* At, const double* Bs, int N16, int i0,
+                                           int j0, int lr, int lk) {
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  const double* pa = At + lk * N16 + i0 + lr;
+  const double* pb = Bs + lk * N16 + j0 + lr;
+#pragma unroll 4
+  for (int k = 0; k < N16; k += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[k * N16], pb[k * N16], acc, 0, 0, 0);
+  return acc;
+}
+
+// exp(X) for N <= EXPM_LDS_N entirely in LDS: the same scaling, Taylor
+// polynomial and Paterson-Stockmeyer scheme as wg_expm below, in two padded
+// buffers, B0 the left operand transposed and B1 the right operand as is.
+// The powers are formed as X^2 = X X, X^3 = X X^2, X^4 = X X^3 with X
+// transposed in B0 throughout.  Each wavefront owns BPW 16 x 16 blocks of
+// every product (blocks wv and wv + NWAVES) and keeps its entries of X, X^2
+// and X^3 in registers for the Horner steps, so a product is its
+// matrix-core instructions between two barriers, with no trip through
+// memory.  The result is written to S + 4 N^2 (row-major).
+template <int BPW>
+__device__ __forceinline__ double* wg_expm_lds(int N, double* S, double* L, const double* a,
+                                               double* out_norm1, int* out_s) {
+  __shared__ double s_norm;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const int N16 = (N + 15) & ~15, NB = N16 * N16;
+  double* B0 = L;
+  double* B1 = L + NB;
+  constexpr int EPT = (EXPM_LDS_N * EXPM_LDS_N + BLOCK - 1) / BLOCK;
+  // stage X (zero-padded), all of a thread's loads issued together
+  double xv[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = tid + q * BLOCK, r = e / N16, c = e - r * N16;
+    xv[q] = (e < NB && r < N && c < N) ? S[r * N + c] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = tid + q * BLOCK;
+    if (e < NB) B1[e] = xv[q];
+  }
+  __syncthreads();
+  // 1-norm: the largest absolute column sum
+  {
+    double v[1] = {0.0};
+    for (int j = tid; j < N; j += BLOCK) {
+      double s = 0.0;
+      for (int i = 0; i < N; ++i) s += fabs(B1[i * N16 + j]);
+      v[0] = nanmax(v[0], s);
+    }
+    block_reduce<1>(v, RED_MAX, &s_norm);
+  }
+  const double nrm = s_norm;
+  int s = 0;
+  if (nrm > TAYLOR18_THETA && nrm <= 1e300)  // non-finite: caller rejects
+    s = (int)ceil(log2(nrm / TAYLOR18_THETA));
+  const double scale = ldexp(1.0, -s);
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = tid + q * BLOCK, r = e / N16, c = e - r * N16;
+    if (e < NB) {
+      B0[c * N16 + r] = xv[q] * scale;
+      B1[e] = xv[q] * scale;
+    }
+  }
+  __syncthreads();
+  const int nb = N16 >> 4;
+  const int lr = lane & 15, lk = lane >> 4;
+  bool act[BPW];
+  int i0[BPW], j0[BPW];
+  double x[BPW][4], x2[BPW][4], x3[BPW][4];
+  bool diag[BPW][4];
+  dbl4 c[BPW];
+#pragma unroll
+  for (int b = 0; b < BPW; ++b) {
+    const int blk = wv + b * NWAVES;
+    act[b] = blk < nb * nb;  // uniform per wavefront
+    i0[b] = act[b] ? (blk / nb) * 16 : 0;
+    j0[b] = act[b] ? (blk - (blk / nb) * nb) * 16 : 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0[b] + lk + 4 * r, j = j0[b] + lr;
+      x[b][r] = act[b] ? B1[i * N16 + j] : 0.0;
+      diag[b][r] = i == j && i < N;
+    }
+  }
+  // C = B0^T B1 for this wavefront's blocks
+  auto product = [&]() {
+#pragma unroll
+    for (int b = 0; b < BPW; ++b)
+      if (act[b]) c[b] = mfma_block(B0, B1, N16, i0[b], j0[b], lr, lk);
+  };
+  // X^2, then X^3 (B1 <- X^2), then X^4 (B1 <- X^3)
+  product();
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BPW; ++b) {
+    if (act[b]) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        x2[b][r] = c[b][r];
+        B1[(i0[b] + lk + 4 * r) * N16 + j0[b] + lr] = c[b][r];
+      }
+    }
+  }
+  __syncthreads();
+  product();
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BPW; ++b) {
+    if (act[b]) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        x3[b][r] = c[b][r];
+        B1[(i0[b] + lk + 4 * r) * N16 + j0[b] + lr] = c[b][r];
+      }
+    }
+  }
+  __syncthreads();
+  product();
+  __syncthreads();
+  // B0 <- X^4 (transposed), B1 <- Y = a16 I + a17 X + a18 X^2
+#pragma unroll
+  for (int b = 0; b < BPW; ++b) {
+    if (act[b]) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0[b] + lk + 4 * r, j = j0[b] + lr;
+        B0[j * N16 + i] = c[b][r];
+        B1[i * N16 + j] = (diag[b][r] ? a[16] : 0.0) + a[17] * x[b][r] + a[18] * x2[b][r];
+      }
+    }
+  }
+  __syncthreads();
+  // Horner in X^4: Y = B_h + X^4 Y for h = 3..0; the last Y also goes to B0
+  // (transposed) as the left operand of the squarings
+  for (int h = 3; h >= 0; --h) {
+    product();
+    __syncthreads();
+    const double a0 = a[4 * h], a1 = a[4 * h + 1], a2 = a[4 * h + 2], a3 = a[4 * h + 3];
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+      if (act[b]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0[b] + lk + 4 * r, j = j0[b] + lr;
+          const double y = c[b][r] + (diag[b][r] ? a0 : 0.0) + a1 * x[b][r] + a2 * x2[b][r] +
+                           a3 * x3[b][r];
+          B1[i * N16 + j] = y;
+          if (h == 0) B0[j * N16 + i] = y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < s; ++k) {
+    product();
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+      if (act[b]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0[b] + lk + 4 * r, j = j0[b] + lr;
+          B0[j * N16 + i] = c[b][r];
+          B1[i * N16 + j] = c[b][r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* E = S + 4 * (size_t)N * N;
+  for (int e = tid; e < N * N; e += BLOCK) {
+    const int r = e / N, cc = e - r * N;
+    E[e] = B1[r * N16 + cc];
+  }
+  if (tid == 0) { *out_norm1 = nrm; *out_s = s; }
+  __syncthreads();
+  return E;
+}
+
 // E = exp(A) for the N x N matrix in S[0] (overwritten).  S must hold 8
 // matrices of N*N doubles (6 are used); L is DENSE_LDS doubles of shared
 // memory.  Returns (in shared out_*) the 1-norm of A and the number of
@@ -240,6 +430,8 @@ __device__ __forceinline__ double* wg_expm(int N, double* S, double* L, double* 
     }
     s_a[19] = 0.0;
   }
+  if (N <= 64) return wg_expm_lds<1>(N, S, L, s_a, out_norm1, out_s);
+  if (N <= EXPM_LDS_N) return wg_expm_lds<2>(N, S, L, s_a, out_norm1, out_s);
   // 1-norm: the largest absolute column sum (the reduction's barriers also
   // publish s_a)
   {
