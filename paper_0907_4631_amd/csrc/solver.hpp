@@ -1091,7 +1091,20 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
     double f[4] = {0.0, 0.0, 0.0, 0.0};  // bad, nonfinite, asym, max row sum
     int cmin = n, cmax = -1;             // columns the own rows reference
     const bool check_sym = P.symm < 0;
+    // the right-hand sides in the same pass: max |b_k| for k < 4, u_0 = b_0
+    // and ||b_0||^2
+    double bmax[4] = {0.0, 0.0, 0.0, 0.0};
+    double usq = 0.0;
     for (int r = rb + tid; r < re; r += BLOCK) {
+      {
+        const double b0 = P.b[r];
+        P.u[r] = b0;
+        usq += b0 * b0;
+        bmax[0] = nanmax(bmax[0], fabs(b0));
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+          if (k <= p) bmax[k] = nanmax(bmax[k], fabs(P.b[(long long)k * P.ldb + r]));
+      }
       const int k0 = P.rp[r], k1 = P.rp[r + 1];
       bool row_ok = true;
       if (P.validate) {
@@ -1163,7 +1176,11 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       }
       f[3] = nanmax(f[3], s);
     }
-    block_reduce<4>(f, RED_MAX, sh.blk);
+    {
+      // sh.blk[0..8): the flags, the largest row sum and max |b_0..3|
+      double f8[8] = {f[0], f[1], f[2], f[3], bmax[0], bmax[1], bmax[2], bmax[3]};
+      block_reduce<8>(f8, RED_MAX, sh.blk);
+    }
     // this workgroup's copy of H starts at zero: the Krylov steps write only
     // each column's window and subdiagonal
     for (size_t e = tid; e < H_WORDS; e += BLOCK) w.Hm[e] = 0.0;
@@ -1185,14 +1202,19 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       }
       __syncthreads();
     }
-    // max |b_k| for every k (one block reduction per column)
-    for (int k = 0; k <= p; ++k) {
+    // max |b_k| for the columns past the first four (one pass each)
+    for (int k = 4; k <= p; ++k) {
       double bm[1] = {0.0};
       const double* bk = P.b + (long long)k * P.ldb;
       for (int r = rb + tid; r < re; r += BLOCK) bm[0] = nanmax(bm[0], fabs(bk[r]));
       block_reduce<1>(bm, RED_MAX, sh.blk + 4 + k);
     }
-    if (!team_sync(tm, sh.blk, 5 + p, RED_MAX, sh.red)) return SOLVE_ABORTED;
+    {
+      double a1[1] = {usq};
+      block_reduce<1>(a1, RED_SUM, sh.blk + 5 + p);
+    }
+    // one team reduction: maxima for the first 5 + p values, ||b_0||^2 summed
+    if (!team_sync(tm, sh.blk, 6 + p, RED_SUM, sh.red, 5 + p)) return SOLVE_ABORTED;
     if (tm.rank == 0 && tid == 0) {
       const double* o = sh.red;
       st->status = ST_OK;
@@ -1247,9 +1269,9 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       st->fp32_err = 0.0;
       st->redo64 = 0;
       st->steps64 = 0;
-      st->unorm = 0.0;
+      st->unorm = sqrt(o[5 + p]);  // u_0 = b_0
       st->bytes = (check_sym ? 2.0 : 1.0) * (sizeof(VT) + 4.0) * P.nnz + 4.0 * (n + 1.0) +
-                  8.0 * n * (p + 1.0);
+                  8.0 * n * (p + 2.0);
       st->bytes_ref = 0.0;
       st->krylov_bytes_ref = 0.0;
       st->krylov_ticks = 0;
@@ -1276,19 +1298,6 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       st->done = 1;
     }
     goto finish;
-  }
-
-  if (!resume) {
-    double a1[1] = {0.0};
-    for (int r = rb + tid; r < re; r += BLOCK) {
-      const double v = P.b[r];
-      P.u[r] = v;
-      a1[0] += v * v;
-    }
-    if (tm.rank == 0 && tid == 0) st->bytes += 16.0 * n;
-    block_reduce<1>(a1, RED_SUM, sh.blk);
-    if (!team_sync(tm, sh.blk, 1, RED_SUM, sh.red)) return SOLVE_ABORTED;
-    if (tm.rank == 0 && tid == 0) st->unorm = sqrt(sh.red[0]);
   }
 
   {

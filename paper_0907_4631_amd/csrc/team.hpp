@@ -248,9 +248,10 @@ __device__ __forceinline__ bool wait_flags(const Team& tm, const unsigned* flags
 // (no write-back of this workgroup's other global writes, no invalidation
 // before later reads of other workgroups' data).  For reductions whose
 // surrounding code reads only its own rows until a full synchronisation.
+// nmax > 0: values k < nmax are reduced with RED_MAX whatever op is.
 template <bool LIGHT = false>
 __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int K, int op,
-                                          double* out) {
+                                          double* out, int nmax = 0) {
   __shared__ unsigned s_epoch;
   const int tid = threadIdx.x;
   if (tm.size == 1) {
@@ -283,13 +284,14 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
       if (!wait_flags<LIGHT>(tm, tm.arr, tm.size, e)) return false;
       const int lane = tid % WAVE, wv = tid / WAVE;
       for (int k = wv; k < K; k += NWAVES) {
-        double a = (op == RED_SUM) ? 0.0 : -INFINITY;
+        const int opk = k < nmax ? RED_MAX : op;
+        double a = (opk == RED_SUM) ? 0.0 : -INFINITY;
         for (int r = lane; r < tm.size; r += WAVE) {
           const double* src = tm.partials + (size_t)r * PS + k;
           const double v = LIGHT ? ld_coh(src) : *src;
-          a = (op == RED_SUM) ? a + v : nanmax(a, v);
+          a = (opk == RED_SUM) ? a + v : nanmax(a, v);
         }
-        a = (op == RED_SUM) ? wave_sum(a) : wave_max(a);
+        a = (opk == RED_SUM) ? wave_sum(a) : wave_max(a);
         if (lane == 0) {
           if (LIGHT) st_coh(tm.result + k, a);
           else tm.result[k] = a;
@@ -329,10 +331,11 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
         const double* src = tm.partials + (size_t)(g0 + r) * PS + k;
         v[r] = r < gsz ? (LIGHT ? ld_coh(src) : *src) : 0.0;
       }
+      const int opk = k < nmax ? RED_MAX : op;
       double a = v[0];
 #pragma unroll
       for (int r = 1; r < TEAM_GROUP; ++r)
-        if (r < gsz) a = (op == RED_SUM) ? a + v[r] : nanmax(a, v[r]);
+        if (r < gsz) a = (opk == RED_SUM) ? a + v[r] : nanmax(a, v[r]);
       if (LIGHT) st_coh(gsum + (size_t)grp * PS + k, a);
       else gsum[(size_t)grp * PS + k] = a;
     }
@@ -357,7 +360,7 @@ __device__ __forceinline__ bool team_sync(const Team& tm, const double* blk, int
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         if (gb + q < ngroups) {
-          a = first ? v[q] : ((op == RED_SUM) ? a + v[q] : nanmax(a, v[q]));
+          a = first ? v[q] : ((k < nmax || op != RED_SUM) ? nanmax(a, v[q]) : a + v[q]);
           first = false;
         }
       }
