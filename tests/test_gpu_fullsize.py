@@ -111,3 +111,14 @@ def test_full_size_learned_proposer_meets_gate(pk):
     u, st, tol = run(pk, "reaction2d-1024-call0", proposer=PR.load())
     assert st["proposals"] > 0
     check("reaction2d-1024-call0", u, tol)
+
+
+def test_full_size_fp32_basis_request_builds_fp64_steps(pk):
+    """The 128^3 Laplacian with the FP32 basis requested: the phi-part of
+    eq. step is far larger than u there, so every step's a-priori rounding
+    bound exceeds the budget and the step is built with the FP64 basis; the
+    result meets the same gate."""
+    print("full-size case laplace3d-128 fp32 basis requested", flush=True)
+    u, st, tol = run(pk, "laplace3d-128", precision=pk.FP32_BASIS, val_dtype=np.float32)
+    assert st["steps"] >= 1 and st["fp64_steps"] == st["steps"]
+    check("laplace3d-128", u, tol)
