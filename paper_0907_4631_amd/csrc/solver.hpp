@@ -359,6 +359,40 @@ __device__ __forceinline__ void phase_dots2(const T* V, long long ldv, int i0, i
   __syncthreads();
 }
 
+// The same sums for a window of at most two columns (windowed Lanczos): one
+// pass in which each thread reads its own rows of the columns, u and w once
+// and forms all 2K + 2 terms (every wavefront busy, u and w read once), then
+// one block reduction in a fixed order.  Layout of blk as phase_dots2's.
+template <typename T>
+__device__ __forceinline__ void phase_dots_window(const T* V, long long ldv, int i0, int K,
+                                                  const T* U, const T* Wv, bool with_u, int rb,
+                                                  int re, Shared& sh) {
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // v0.w, v1.w, v0.u, v1.u, u.u, u.w
+  const T* va = V + (long long)i0 * ldv;
+  const T* vb = va + ldv;
+  for (int r = rb + (int)threadIdx.x; r < re; r += BLOCK) {
+    const double u = (double)U[r], w = (double)Wv[r];
+    const double a = K > 0 ? (double)va[r] : 0.0;
+    const double b = K > 1 ? (double)vb[r] : 0.0;
+    acc[0] += a * w;
+    acc[1] += b * w;
+    acc[2] += a * u;
+    acc[3] += b * u;
+    acc[4] += u * u;
+    acc[5] += u * w;
+  }
+  block_reduce<6>(acc, RED_SUM, sh.qv);
+  for (int k = threadIdx.x; k < K; k += BLOCK) {
+    sh.blk[k] = sh.qv[k];
+    sh.blk[K + k] = with_u ? sh.qv[2 + k] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    sh.blk[2 * K] = sh.qv[4];
+    sh.blk[2 * K + 1] = sh.qv[5];
+  }
+  __syncthreads();
+}
+
 // Team-uniform state of an incremental Krylov build.  Columns 0..have-1 of
 // V are final; U holds the candidate for column `have` (orthogonalised once,
 // not normalised) unless u_final, when it holds v_have itself.  Columns
@@ -483,7 +517,9 @@ __device__ __forceinline__ bool krylov_iter(const Team& tm, const Problem& P, co
   // P2: one reduction over the window [zb, j)
   const int zb = lanczos ? (j > 2 ? j - 2 : 0) : 0;
   const int K = j - zb;
-  phase_dots2<T>(w.V, w.ldv, zb, K, U, Wv, !uf, rb, re, sh);
+  // (the own rows of u and w were written by these same threads)
+  if (lanczos) phase_dots_window<T>(w.V, w.ldv, zb, K, U, Wv, !uf, rb, re, sh);
+  else phase_dots2<T>(w.V, w.ldv, zb, K, U, Wv, !uf, rb, re, sh);
   if (!team_sync<true>(tm, sh.blk, 2 * K + 2, RED_SUM, sh.red)) return false;
   const double a = sh.red[2 * K], c = sh.red[2 * K + 1];
   // z -> sh.red[0..K), s -> sh.h1[0..K)
