@@ -6,9 +6,11 @@
  * for a large sparse matrix A in CSR form (Niesen & Wright, eq. lincomb2 /
  * eq. phide), by time stepping (eq. step, eq. wrecurrence), Arnoldi or Lanczos
  * projection with classical Gram-Schmidt applied twice, the exponential of the
- * augmented Hessenberg matrix (eq. hathm, degree-13 Pade with scaling and
- * squaring), the corrector eq. phipapprox2 and the error estimate eq. errest
- * that adapts the substep tau and the Krylov dimension m (Algorithms 3 and 4).
+ * augmented Hessenberg matrix (eq. hathm, by scaling and squaring; the paper's
+ * degree-13 Pade approximant is replaced by a degree-18 Taylor polynomial of
+ * the same double-precision backward error), the corrector eq. phipapprox2
+ * and the error estimate eq. errest that adapts the substep tau and the Krylov
+ * dimension m (Algorithms 3 and 4).
  *
  * Plain C ABI.  All array arguments marked "device" are HIP device pointers;
  * the caller owns every buffer (matrix, vectors, workspace).  The library
