@@ -425,6 +425,34 @@ def run_integrator(args):
         res[name]["max_diff_vs_plain_cold"] = float(np.linalg.norm(outs[name] - ref) /
                                                     max(1.0, np.linalg.norm(ref)))
     ms = res["learned"]["ms_per_step"]
+    cpu = err = None
+    if not args.no_cpu:
+        # the first steps against the same integrator driven by the CPU oracle
+        # (also its time per step on the host cores)
+        import oracle
+        import scipy.sparse as sp
+        oracle.build(force=False)
+        k = 3
+        log(f"integrator: {k} steps with the CPU oracle")
+        u = np.array(u0, dtype=np.float64)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            F = lap @ u + u - u ** 3
+            J = sp.csr_matrix(lap + sp.diags(1.0 - 3.0 * u * u))
+            J.sort_indices()
+            du, _ = oracle.phipm(h, J, np.stack([np.zeros(N * N), F], axis=1), tol=tol, symm=1)
+            u = u + du
+        sec = (time.perf_counter() - t0) / k
+        cpu = {"value": 1.0 / sec, "unit": "solves/s", "cores": oracle.threads(),
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"the first {k} integrator steps (plain step control)"}
+        err = {"steps": k}
+        for name in ("learned", "plain-cold"):
+            kw = {"proposer": PR.load()} if name == "learned" else {}
+            ig = integrator.AllenCahnERE(lap, u0, h, tol=tol, **kw)
+            ig.run(k)
+            g = ig.u.cpu().numpy()
+            err[name] = float(np.linalg.norm(g - u) / np.linalg.norm(u))
     line = {
         "metric": METRIC, "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -432,33 +460,50 @@ def run_integrator(args):
         "config": {"workload": WORKLOADS["allencahn-1024-ere"][1], "n": N * N, "h": h,
                    "integrator_steps": steps, "variants": res},
     }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+        line["err_vs_oracle"] = err
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline_batch(probs, gpu_stats, budget_s=20.0, seed=7):
+def cpu_baseline_batch(probs, gpu_stats, us=None, budget_s=20.0, seed=7):
     """The oracle on the host cores, timed on a seeded random sample of the
     batch's instances (about budget_s of CPU work) and scaled to the whole
-    batch by rows x products (the GPU run's product counts)."""
+    batch by rows x products (the GPU run's product counts).  With the GPU's
+    outputs us, also the error of those instances against the oracle: the
+    largest ||u - u_ref|| / (10 tol max(1, ||u_ref||)) (the batch's parity
+    gate; below 1 passes) and the largest relative 2-norm error."""
     import oracle
     oracle.build(force=False)
     order = np.random.default_rng(seed).permutation(len(probs))
     spent, work_done, done = 0.0, 0.0, 0
+    worst_gate, worst_rel = 0.0, 0.0
     for i in order:
         pb = probs[i]
         w = pb.n * max(1, gpu_stats[i]["matvecs"])
         t0 = time.perf_counter()
-        oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol)
+        ref, _ = oracle.phipm(pb.t, pb.A, pb.b, tol=pb.tol)
         spent += time.perf_counter() - t0
         work_done += w
         done += 1
+        if us is not None:
+            u = us[i].cpu().numpy()
+            nr = float(np.linalg.norm(ref))
+            d = float(np.linalg.norm(u - ref))
+            worst_gate = max(worst_gate, d / (10.0 * pb.tol * max(1.0, nr)))
+            worst_rel = max(worst_rel, d / max(nr, 1e-300))
         if spent > budget_s:
             break
     total = sum(pb.n * max(1, s["matvecs"]) for pb, s in zip(probs, gpu_stats))
     per_batch = spent * total / work_done
-    return {"value": len(probs) / per_batch, "unit": "solves/s", "cores": oracle.threads(),
-            "kind": "oracle", "cpu_model": cpu_model(),
-            "sample": f"{done} randomly chosen of the {len(probs)} instances ({spent:.1f} s), "
-                      f"scaled to the batch by rows x products"}
+    out = {"value": len(probs) / per_batch, "unit": "solves/s", "cores": oracle.threads(),
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{done} randomly chosen of the {len(probs)} instances ({spent:.1f} s), "
+                     f"scaled to the batch by rows x products"}
+    if us is not None:
+        out["sampled_err"] = {"instances": done, "max_err_over_gate": worst_gate,
+                              "max_rel_err": worst_rel}
+    return out
 
 
 def run_batch(args):
@@ -527,7 +572,8 @@ def run_batch(args):
     }
     if not args.no_cpu:
         log("batch: CPU oracle sample")
-        line["cpu_baseline"] = cpu_baseline_batch(probs, st)
+        line["cpu_baseline"] = cpu_baseline_batch(probs, st, us)
+        line["err_vs_oracle"] = line["cpu_baseline"]["sampled_err"]
     print(json.dumps(line), flush=True)
     plan.close()
 
