@@ -1131,6 +1131,8 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
     // and ||b_0||^2
     double bmax[4] = {0.0, 0.0, 0.0, 0.0};
     double usq = 0.0;
+    // entries above the diagonal minus entries below it (symmetry test)
+    double cdiff = 0.0;
     for (int r = rb + tid; r < re; r += BLOCK) {
       {
         const double b0 = P.b[r];
@@ -1150,6 +1152,7 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       }
       double s = 0.0;
       int prev = -1;
+      int kup = k1;  // the row's first entry above the diagonal
       // (loops below avoid `break`: the compiler has dropped flag updates
       // after early exits from nested divergent loops)
       for (int k = k0; k < k1 && row_ok; ++k) {
@@ -1164,13 +1167,22 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
           cmax = c > cmax ? c : cmax;
           if (!isfinite(a)) f[1] = 1.0;
           s += fabs(a);
+          if (check_sym) {
+            cdiff += c > r ? 1.0 : (c < r ? -1.0 : 0.0);
+            kup = (c > r && k < kup) ? k : kup;
+            if (c == r && !(a == a)) f[2] = 1.0;  // a_rr == a_rr fails for NaN
+          }
         }
       }
       if (check_sym && row_ok) {
-        // a_rc == a_cr for every entry: binary searches of rows c for column
-        // r, eight entries of the row at a time in lock step, so that their
-        // loads are in flight together (the searches are latency-bound)
-        for (int kb = k0; kb < k1; kb += 8) {
+        // a_rc == a_cr for every entry above the diagonal: binary searches of
+        // rows c for column r, eight entries of the row at a time in lock
+        // step, so that their loads are in flight together.  In a CSR matrix
+        // with sorted, distinct columns in each row, mirroring maps the
+        // entries above the diagonal one-to-one onto entries below it, so
+        // with as many entries below as above (cdiff summed to zero over the
+        // whole matrix) every entry below is covered as well.
+        for (int kb = kup; kb < k1; kb += 8) {
           int lo[8], hi[8], pos[8];
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
@@ -1246,11 +1258,12 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       block_reduce<1>(bm, RED_MAX, sh.blk + 4 + k);
     }
     {
-      double a1[1] = {usq};
-      block_reduce<1>(a1, RED_SUM, sh.blk + 5 + p);
+      double a2[2] = {usq, cdiff};
+      block_reduce<2>(a2, RED_SUM, sh.blk + 5 + p);
     }
-    // one team reduction: maxima for the first 5 + p values, ||b_0||^2 summed
-    if (!team_sync(tm, sh.blk, 6 + p, RED_SUM, sh.red, 5 + p)) return SOLVE_ABORTED;
+    // one team reduction: maxima for the first 5 + p values, ||b_0||^2 and
+    // the count difference summed
+    if (!team_sync(tm, sh.blk, 7 + p, RED_SUM, sh.red, 5 + p)) return SOLVE_ABORTED;
     if (tm.rank == 0 && tid == 0) {
       const double* o = sh.red;
       st->status = ST_OK;
@@ -1264,8 +1277,9 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       double bn = o[4];
       for (int k = 1; k <= p && bn == 0.0; ++k) bn = o[4 + k];
       st->bnorm = bn;
-      st->lanczos = P.symm < 0 ? (o[2] == 0.0) : (P.symm != 0);
-      st->setup_flags = (o[0] != 0.0 ? 1 : 0) | (o[1] != 0.0 ? 2 : 0) | (o[2] != 0.0 ? 4 : 0);
+      const bool asym = o[2] != 0.0 || o[6 + p] != 0.0;
+      st->lanczos = P.symm < 0 ? !asym : (P.symm != 0);
+      st->setup_flags = (o[0] != 0.0 ? 1 : 0) | (o[1] != 0.0 ? 2 : 0) | (asym ? 4 : 0);
       st->zero_path = (st->anorm == 0.0 || bn == 0.0 || st->t_end == 0.0);
       st->m_cap = P.m_max < n ? P.m_max : n;
       double tau;
@@ -1306,7 +1320,8 @@ __device__ __forceinline__ int solve(const Team& tm, const Problem& P, const Wor
       st->redo64 = 0;
       st->steps64 = 0;
       st->unorm = sqrt(o[5 + p]);  // u_0 = b_0
-      st->bytes = (check_sym ? 2.0 : 1.0) * (sizeof(VT) + 4.0) * P.nnz + 4.0 * (n + 1.0) +
+      // (the mirror searches read about half the entries again)
+      st->bytes = (check_sym ? 1.5 : 1.0) * (sizeof(VT) + 4.0) * P.nnz + 4.0 * (n + 1.0) +
                   8.0 * n * (p + 2.0);
       st->bytes_ref = 0.0;
       st->krylov_bytes_ref = 0.0;

@@ -218,6 +218,55 @@ def test_adaptive_matches_oracle(pk, name, build, p, t, tol):
     assert st["anorm"] == pytest.approx(abs(A).sum(axis=1).max(), rel=1e-14)
 
 
+def _with_entries(A, entries):
+    """A copy of CSR matrix A with the (row, col, value) entries set (added
+    where absent, explicit zeros kept), columns sorted in each row."""
+    M = A.tocoo()
+    rows, cols, vals = list(M.row), list(M.col), list(M.data)
+    where = {(int(r), int(c)): k for k, (r, c) in enumerate(zip(rows, cols))}
+    for r, c, v in entries:
+        if (r, c) in where:
+            vals[where[(r, c)]] = v
+        else:
+            rows.append(r)
+            cols.append(c)
+            vals.append(v)
+    B = sp.csr_matrix((np.array(vals, dtype=np.float64), (np.array(rows), np.array(cols))),
+                      shape=A.shape)
+    B.sort_indices()
+    B.indptr = B.indptr.astype(np.int32)
+    B.indices = B.indices.astype(np.int32)
+    return B
+
+
+_L30 = W.laplace2d(30)   # 900 rows; (31, 1) and (1, 31) are a coupled pair
+SYMMETRY = [
+    ("laplacian", [], True),
+    ("mirrored pair added", [(700, 3, -0.5), (3, 700, -0.5)], True),
+    ("entry below the diagonal without mirror", [(700, 3, -0.5)], False),
+    ("entry above the diagonal without mirror", [(3, 700, -0.5)], False),
+    ("explicit zero below the diagonal without mirror", [(700, 3, 0.0)], False),
+    ("value changed below the diagonal", [(31, 1, -1.5)], False),
+    ("value changed above the diagonal", [(1, 31, -1.5)], False),
+]
+
+
+@pytest.mark.parametrize("name,entries,symmetric", SYMMETRY)
+def test_symmetry_decision_matches_oracle(pk, name, entries, symmetric):
+    """The setup's exact symmetry test (same pattern, bitwise-equal values)
+    picks Lanczos exactly when the oracle's entry-by-entry test does,
+    including asymmetries present on one side of the diagonal only."""
+    say("symmetry case", name)
+    A = _with_entries(_L30, entries)
+    assert oracle.is_symmetric(A) == symmetric
+    b = np.random.default_rng(9).standard_normal((A.shape[0], 2))
+    u, st = gpu_solve(pk, 1e-3, A, b, tol=1e-9)
+    ref, _ = oracle.phipm(1e-3, A, b, tol=1e-9)
+    assert st["lanczos"] == int(symmetric)
+    assert (st["setup_flags"] >> 2 & 1) == int(not symmetric)
+    assert rel(u, ref) <= 1e-8
+
+
 @pytest.mark.parametrize("mode", ["fixed", "adaptive"])
 def test_full_reorth_lanczos_matches_oracle(pk, mode):
     """Lanczos with CGS2 against every basis vector (Algorithm 2 with full
