@@ -484,6 +484,40 @@ def test_symmetry_detection(oracle_lib):
     assert oracle.is_symmetric(W.reaction2d(16, 3))
 
 
+@pytest.mark.parametrize("entries", [
+    [],
+    [(70, 3, -0.5), (3, 70, -0.5)],      # a mirrored pair added
+    [(70, 3, -0.5)],                     # below the diagonal, no mirror
+    [(3, 70, -0.5)],                     # above the diagonal, no mirror
+    [(70, 3, 0.0)],                      # explicit zero, no mirror
+    [(11, 1, -7.0)],                     # one value changed below the diagonal
+    [(1, 11, -7.0)],                     # one value changed above the diagonal
+    [(5, 5, -1.0)],                      # a diagonal value changed
+])
+def test_symmetry_detection_one_sided_edits(oracle_lib, entries):
+    """Exact symmetry (same stored pattern, equal values) against its
+    definition on the dense matrix and the set of stored positions."""
+    A = W.laplace2d(10).tocoo()
+    rows, cols, vals = list(A.row), list(A.col), list(A.data)
+    where = {(int(r), int(c)): k for k, (r, c) in enumerate(zip(rows, cols))}
+    for r, c, v in entries:
+        if (r, c) in where:
+            vals[where[(r, c)]] = v
+        else:
+            rows.append(r)
+            cols.append(c)
+            vals.append(v)
+    B = sp.csr_matrix((np.array(vals), (np.array(rows), np.array(cols))), shape=A.shape)
+    B.sort_indices()
+    B.indptr = B.indptr.astype(np.int32)
+    B.indices = B.indices.astype(np.int32)
+    stored = {(i, int(j)) for i in range(B.shape[0])
+              for j in B.indices[B.indptr[i]:B.indptr[i + 1]]}
+    dense = B.toarray()
+    want = stored == {(j, i) for i, j in stored} and np.array_equal(dense, dense.T)
+    assert oracle.is_symmetric(B) == want
+
+
 def test_oracle_spmv_matches_scipy(oracle_lib):
     A = W.convdiff2d(40, 30.0, 10.0)
     x = np.random.default_rng(0).standard_normal(A.shape[0])
